@@ -1,0 +1,494 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks one oracle function against something other than the oracle
+itself: published test vectors, brute force on tiny inputs, closed forms,
+exact invariants, or hand-derived worked examples under tests/golden/.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+# ---------------------------------------------------------------------------
+# Uniform source: splitmix64 against its published vectors
+# ---------------------------------------------------------------------------
+
+def test_splitmix64_published_vectors():
+    g = _golden("splitmix64_vectors.json")
+    s = 1234567
+    got = []
+    for _ in range(5):
+        s, z = oracle.splitmix64(s)
+        got.append(str(z))
+    assert got == g["seed_1234567_first5"]
+    _, z0 = oracle.splitmix64(0)
+    assert z0 == int(g["seed_0_first"], 16)
+
+
+def test_splitmix64_published_bucket_counts():
+    g = _golden("splitmix64_vectors.json")
+    s = 987654321
+    counts = [0] * 5
+    for _ in range(100000):
+        s, z = oracle.splitmix64(s)
+        counts[(z * 5) >> 64] += 1
+    assert counts == g["seed_987654321_buckets5_of_100000"]
+
+
+# ---------------------------------------------------------------------------
+# Strides and offsets (eq. 1, eq. 2, sections 3 and 8)
+# ---------------------------------------------------------------------------
+
+def test_stride_pairs_start_with_rann4_sets():
+    # Section 8: alpha in {3, 5}, beta in {7, 11}.
+    assert oracle.stride_pair(0) == (3, 5)
+    assert oracle.stride_pair(1) == (7, 11)
+
+
+def test_stride_pairs_odd_distinct_greater_than_one():
+    # Sections 3 and 7: strides odd, distinct and greater than 1.
+    flat = [x for k in range(16) for x in oracle.stride_pair(k)]
+    assert len(set(flat)) == 32
+    assert all(x % 2 == 1 and x > 1 for x in flat)
+    for x in flat:
+        assert all(x % d for d in range(2, int(math.isqrt(x)) + 1))
+
+
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 32, 64])
+def test_affine_index_map_is_permutation_iff_gcd_one(N):
+    # eq. 2 by brute force: j -> (a j + b) mod N is a bijection exactly when
+    # GCD(a, N) = 1, i.e. for every odd a when N is a power of two.
+    for a in range(N):
+        for b in range(N):
+            image = {(a * j + b) % N for j in range(N)}
+            assert (len(image) == N) == (math.gcd(a, N) == 1)
+
+
+@pytest.mark.parametrize("n,N", [(4, 2), (4, 8), (4, 256), (16, 16), (16, 1024),
+                                 (4, 1 << 22)])
+@pytest.mark.parametrize("a_mode", [oracle.A_PAIRS, oracle.A_FULL_ODD])
+def test_pass_params_ranges(n, N, a_mode):
+    s = 99
+    seen_hi = [set() for _ in range(n)]
+    for _ in range(200):
+        a, b, signs, s = oracle.pass_params(s, n, N, a_mode)
+        assert signs == 0 if n == 4 else signs < (1 << 16)
+        assert np.all(a % 2 == 1) and np.all(a < N) and np.all(b < N)
+        if a_mode == oracle.A_PAIRS:
+            for k in range(n):
+                pair = oracle.stride_pair(k)
+                assert a[k] in (pair[0] % N, pair[1] % N)
+                seen_hi[k].add(int(a[k]))
+    if a_mode == oracle.A_PAIRS and N > 137:
+        assert all(len(x) == 2 for x in seen_hi)  # both members get picked
+
+
+def test_pass_params_consume_one_draw_per_component():
+    s0 = 12345
+    _, _, _, s = oracle.pass_params(s0, 16, 64)
+    assert s == (s0 + 16 * 0x9E3779B97F4A7C15) % (1 << 64)
+
+
+def test_offsets_uniform():
+    # Section 8: offsets uniform on {0..N-1}. Chi-squared over 16 cells.
+    s = 7
+    N = 16
+    counts = np.zeros(N)
+    for _ in range(4000):
+        _, b, _, s = oracle.pass_params(s, 4, N)
+        np.add.at(counts, b.astype(int), 1)
+    expect = counts.sum() / N
+    chi2 = ((counts - expect) ** 2 / expect).sum()
+    assert chi2 < 15 + 5 * math.sqrt(30)
+
+
+# ---------------------------------------------------------------------------
+# Matrices: orthogonal, rows with at least two non-small entries (section 3)
+# ---------------------------------------------------------------------------
+
+def _sylvester(n):
+    H = np.array([[1]])
+    while H.shape[0] < n:
+        H = np.kron(H, np.array([[1, 1], [1, -1]]))
+    return H
+
+
+def _expected_matrix(n, mat):
+    if n == 4 and mat == 1:
+        return 0.5 * np.ones((4, 4)) - np.eye(4)
+    return _sylvester(n) / math.sqrt(n)
+
+
+@pytest.mark.parametrize("n,mat", [(4, 0), (4, 1), (16, 0)])
+def test_dense_matrix_definition_and_orthogonality(n, mat):
+    M = oracle.matrix(n, mat)
+    assert np.array_equal(M, _expected_matrix(n, mat))
+    assert np.array_equal(M @ M.T, np.eye(n))  # exact in binary
+    for row in M:
+        nz = np.abs(row[row != 0])
+        assert nz.size >= 2 and nz.min() >= 0.25
+
+
+def test_a0_a1_generate_a_finite_group():
+    # The paper's footnote asks for multiplicatively independent matrices;
+    # A0 and A1 are involutions and A0 A1 has order 6 (a dihedral group of
+    # order 12). This records that reading; the per-pass permutations carry
+    # the mixing.
+    A0, A1 = oracle.matrix(4, 0), oracle.matrix(4, 1)
+    assert np.array_equal(A0 @ A0, np.eye(4))
+    assert np.array_equal(A1 @ A1, np.eye(4))
+    P = A0 @ A1
+    Q = np.eye(4)
+    orders = []
+    for m in range(1, 13):
+        Q = Q @ P
+        if np.allclose(Q, np.eye(4), atol=1e-12):
+            orders.append(m)
+    assert orders[0] == 6
+
+
+# ---------------------------------------------------------------------------
+# One pass: brute-force impulse responses pin gather, matrix and write-back
+# ---------------------------------------------------------------------------
+
+def _preimage(a, b, x, N):
+    hits = [j for j in range(N) if (a * j + b) % N == x]
+    assert len(hits) == 1
+    return hits[0]
+
+
+@pytest.mark.parametrize("n,N,mat", [(4, 8, 0), (4, 8, 1), (4, 32, 0),
+                                     (4, 32, 1), (16, 4, 0), (16, 16, 0)])
+def test_pass32_impulse_response(n, N, mat):
+    # eq. 1: new tuple j takes component k from old X_k[(a_k j + b_k) mod N].
+    # An impulse at X_k[x] must land in exactly one new tuple, j*, carrying
+    # column k of the matrix (h folds in the 1/2 or 1/4 factor; for n = 16
+    # the column is negated when bit k of the sign mask is set).
+    rng = np.random.default_rng(n * 1000 + N + mat)
+    A = _expected_matrix(n, mat)
+    h = np.float32(0.5 if n == 4 else 0.25)
+    for _ in range(3):
+        a = (rng.integers(0, N, size=n) | 1).astype(np.uint32)
+        b = rng.integers(0, N, size=n).astype(np.uint32)
+        signs = int(rng.integers(0, 1 << 16)) if n == 16 else 0
+        for k in range(n):
+            for x in range(N):
+                X = np.zeros(n * N, dtype=np.float32)
+                X[k * N + x] = 1.0
+                Y = oracle.pass32(n, N, mat, a, b, h, X, signs).reshape(n, N)
+                js = _preimage(int(a[k]), int(b[k]), x, N)
+                expect = np.zeros((n, N))
+                expect[:, js] = A[:, k] * (-1.0 if (signs >> k) & 1 else 1.0)
+                assert np.array_equal(Y.astype(np.float64), expect)
+                Z = oracle.pass64(n, N, mat, a, b, 1.0,
+                                  X.astype(np.float64), signs).reshape(n, N)
+                assert np.array_equal(Z, expect)
+
+
+@pytest.mark.parametrize("n,N,mat", [(4, 64, 0), (4, 64, 1), (16, 32, 0)])
+def test_pass32_equals_dense_product_on_dyadic_inputs(n, N, mat):
+    # With dyadic inputs every partial sum is exact, so the FP32 butterfly
+    # order must reproduce the dense FP64 product bit for bit.
+    rng = np.random.default_rng(5)
+    X = (rng.integers(-64, 65, size=n * N) / 8.0).astype(np.float32)
+    a = (rng.integers(0, N, size=n) | 1).astype(np.uint32)
+    b = rng.integers(0, N, size=n).astype(np.uint32)
+    h = np.float32(0.5 if n == 4 else 0.25)
+    signs = 0xA5C3 if n == 16 else 0
+    Y32 = oracle.pass32(n, N, mat, a, b, h, X, signs)
+    Y64 = oracle.pass64(n, N, mat, a, b, 1.0, X.astype(np.float64), signs)
+    assert np.array_equal(Y32.astype(np.float64), Y64)
+
+
+@pytest.mark.parametrize("n,N,mat", [(4, 256, 0), (4, 256, 1), (16, 256, 0)])
+def test_pass_preserves_sum_of_squares_when_unscaled(n, N, mat):
+    # Section 2: an orthogonal A keeps the sum of squares, up to rounding.
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal(n * N).astype(np.float32)
+    a = (rng.integers(0, N, size=n) | 1).astype(np.uint32)
+    b = rng.integers(0, N, size=n).astype(np.uint32)
+    h = np.float32(0.5 if n == 4 else 0.25)
+    Y = oracle.pass32(n, N, mat, a, b, h, X)
+    s0, s1 = oracle.sumsq_f64(X), oracle.sumsq_f64(Y)
+    assert abs(s1 - s0) <= 8 * 2.0 ** -24 * s0
+    # every old value is used exactly once: the multiset of |values| of the
+    # gathered tuples is the old pool (checked via the impulse test), and the
+    # pass is not a per-tuple map (per-component permutations mix tuples)
+    norms_old = np.sort((X.reshape(n, N) ** 2).sum(0))
+    norms_new = np.sort((Y.reshape(n, N) ** 2).sum(0))
+    assert not np.allclose(norms_old, norms_new, rtol=1e-3)
+
+
+# ---------------------------------------------------------------------------
+# Sum of squares: canonical tree against exact sums and worked examples
+# ---------------------------------------------------------------------------
+
+def test_canonical_tree_worked_examples():
+    g = _golden("canonical_tree.json")
+    c0, c1, c2 = g["cases"]
+    y = np.array(c0["y"], dtype=np.float32)
+    assert oracle.sumsq_f64(y) == float(int(c0["f64_tree"]))
+    y = np.array(c1["y"], dtype=np.float32)
+    assert float(oracle.sumsq_f32(y)) == float(int(c1["f32_tree"]))
+    y = np.array(c2["y"], dtype=np.float32)
+    assert oracle.sumsq_f32c(y) == float(int(c2["f32c_tree"]))
+
+
+@pytest.mark.parametrize("nu", [2, 16, 1024, 4096])
+def test_sumsq_within_error_bound_of_exact(nu):
+    rng = np.random.default_rng(nu)
+    y = (rng.standard_normal(nu) * np.exp(rng.uniform(-3, 3, nu))).astype(np.float32)
+    exact = sum(Fraction(float(v)) ** 2 for v in y)
+    levels = int(math.log2(nu))
+    t64 = Fraction(oracle.sumsq_f64(y))
+    assert abs(t64 - exact) <= Fraction(levels * 2.0 ** -53) * exact
+    t32 = Fraction(float(oracle.sumsq_f32(y)))
+    assert abs(t32 - exact) <= Fraction((levels + 1) * 2.0 ** -24) * exact
+    tc = Fraction(oracle.sumsq_f32c(y))
+    assert abs(tc - exact) <= Fraction(2.0 ** -40) * exact
+    td = Fraction(oracle.sumsq_d(y.astype(np.float64)))
+    assert abs(td - exact) <= Fraction(levels * 2.0 ** -53) * exact
+
+
+def test_sumsq_tree_is_aligned_block_decomposable():
+    # The canonical tree over a power-of-two block is the join of the trees
+    # over its two halves.
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(4096).astype(np.float32)
+    assert oracle.sumsq_f64(y) == oracle.sumsq_f64(y[:2048]) + oracle.sumsq_f64(y[2048:])
+    assert oracle.sumsq_f32(y) == np.float32(oracle.sumsq_f32(y[:2048]) + oracle.sumsq_f32(y[2048:]))
+
+
+# ---------------------------------------------------------------------------
+# Chi-squared rescaling (section 4, eq. 3)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nu", [16, 256])
+def test_chi2_sample_closed_form_moments(nu):
+    # S = (x + sqrt(2 nu - 1))^2 / 2 with x ~ N(0,1): E[S] = nu and
+    # Var[S] = 2 nu - 1/2 (chi2_nu has nu and 2 nu). One independent sample
+    # per seed: the first pass uses the Box-Muller pool's last value.
+    S = []
+    for seed in range(4000):
+        g = oracle.Gen(seed, 4, nu // 4)
+        g.do_pass()
+        S.append(g.last_S)
+    S = np.array(S)
+    m = len(S)
+    var = 2 * nu - 0.5
+    assert abs(S.mean() - nu) <= 5 * math.sqrt(var / m)
+    # variance of the sample variance for this law ~ (mu4 - var^2)/m; use a
+    # generous 10% band, still far from the 2 nu + 1/2 or 4 nu of a wrong S
+    assert abs(S.var() / var - 1) < 0.1
+
+
+def test_scaled_pass_hits_chi2_target():
+    # After a pass the pool's sum of squares equals S up to rounding.
+    g = oracle.Gen(1, 4, 1024)
+    for _ in range(20):
+        g.do_pass()
+        assert abs(g.sigma / g.last_S - 1) < 1e-6
+
+
+def test_chi2_target_depends_only_on_driver():
+    # The new sum of squares depends on the old pool only through its last
+    # flat value (the driver), whatever the rest holds.
+    rng = np.random.default_rng(8)
+    n, N = 4, 64
+    nu = n * N
+    a = np.array([3, 7, 13, 19], dtype=np.uint32)
+    b = np.array([1, 2, 3, 4], dtype=np.uint32)
+    results = []
+    for trial in range(3):
+        X = rng.standard_normal(nu).astype(np.float32)
+        X[-1] = np.float32(0.75)
+        c32, S, _ = oracle.scale32(float(X[-1]), oracle.sumsq_f64(X), nu)
+        Y = oracle.pass32(n, N, 0, a, b, np.float32(c32 * np.float32(0.5)), X)
+        results.append(oracle.sumsq_f64(Y))
+    assert max(results) / min(results) - 1 < 1e-6
+    X[-1] = np.float32(-0.75)
+    c32, S2, _ = oracle.scale32(float(X[-1]), oracle.sumsq_f64(X), nu)
+    assert abs(S2 - S) > 1.0
+
+
+def test_outlier_bound_generalised():
+    # Section 8 bounds the pool maximum across a pass by M/sqrt(2) <= M' <=
+    # sqrt(2) M for n = 2. With entries +-1/2 (n = 4) the same argument gives
+    # c M / 2 <= M' <= 2 c M, and with H16/4, c M / 4 <= M' <= 4 c M.
+    for n, N, lo, hi in ((4, 256, 0.5, 2.0), (16, 64, 0.25, 4.0)):
+        g = oracle.Gen(3, n, N)
+        M = np.abs(g.pool).max()
+        for _ in range(50):
+            g.do_pass()
+            M2 = np.abs(g.pool).max()
+            c = g.last_c64
+            assert c * M * lo * (1 - 1e-6) <= M2 <= c * M * hi * (1 + 1e-6)
+            M = M2
+
+
+# ---------------------------------------------------------------------------
+# Initial pool (section 5: Box-Muller)
+# ---------------------------------------------------------------------------
+
+def test_box_muller_polar_form():
+    seed = 42
+    pool, _ = oracle.initial_pool64(seed, 4, 64)
+    s = seed
+    for m in range(pool.size // 2):
+        s, w1 = oracle.splitmix64(s)
+        s, w2 = oracle.splitmix64(s)
+        u1 = ((w1 >> 11) + 1) * 2.0 ** -53
+        u2 = (w2 >> 11) * 2.0 ** -53
+        x, y = pool[2 * m], pool[2 * m + 1]
+        assert math.isclose(x * x + y * y, -2.0 * math.log(u1), rel_tol=1e-12, abs_tol=1e-300)
+        ang = math.atan2(y, x) % (2 * math.pi)
+        d = abs(ang - 2 * math.pi * u2)
+        assert min(d, 2 * math.pi - d) < 1e-9
+
+
+def test_initial_pool_state_and_moments():
+    pool, s = oracle.initial_pool64(42, 4, 1 << 16)
+    assert s == (42 + pool.size * 0x9E3779B97F4A7C15) % (1 << 64)
+    M = pool.size
+    assert abs(pool.mean()) < 5 * math.sqrt(1 / M)
+    assert abs((pool ** 2).mean() - 1) < 5 * math.sqrt(2 / M)
+    assert abs((pool ** 4).mean() - 3) < 5 * math.sqrt(96 / M)
+
+
+# ---------------------------------------------------------------------------
+# Generator-level properties
+# ---------------------------------------------------------------------------
+
+def test_stream_independent_of_call_splitting():
+    ref = oracle.Gen(42, 4, 64).fill(5000)
+    rng = np.random.default_rng(0)
+    g = oracle.Gen(42, 4, 64)
+    parts, left = [], 5000
+    while left:
+        m = int(min(left, rng.integers(0, 700)))
+        parts.append(g.fill(m))
+        left -= m
+    assert np.array_equal(np.concatenate(parts), ref)
+
+
+def test_throwaway_factor_keeps_every_fth_pool():
+    nu = 4 * 32
+    full = oracle.Gen(9, 4, 32).fill(6 * nu).reshape(6, nu)
+    f2 = oracle.Gen(9, 4, 32, f=2).fill(3 * nu).reshape(3, nu)
+    assert np.array_equal(f2, full[1::2])
+
+
+def test_withheld_driver_is_not_emitted():
+    nu = 4 * 32
+    full = oracle.Gen(9, 4, 32).fill(4 * nu).reshape(4, nu)
+    w = oracle.Gen(9, 4, 32, withhold=1).fill(4 * (nu - 1)).reshape(4, nu - 1)
+    assert np.array_equal(w, full[:, :-1])
+
+
+def test_generator_composes_documented_steps():
+    # The generator is params -> scale from the old pool -> pass with
+    # A_{(p-1) mod 2} -> new sum of squares.
+    n, N = 4, 128
+    g = oracle.Gen(77, n, N)
+    X = g.pool
+    sigma, s = g.sigma, 77 + n * N * 0x9E3779B97F4A7C15
+    s %= 1 << 64
+    assert sigma == oracle.sumsq_f64(X)
+    for p in range(1, 5):
+        a, b, _, s = oracle.pass_params(s, n, N)
+        c32, _, _ = oracle.scale32(float(X[-1]), sigma, n * N)
+        X = oracle.pass32(n, N, (p - 1) % 2, a, b, np.float32(c32 * np.float32(0.5)), X)
+        sigma = oracle.sumsq_f64(X)
+        g.do_pass()
+        assert np.array_equal(g.pool, X)
+        assert g.sigma == sigma and g.rng == s
+
+
+def test_fp32_variant_within_1e5_of_fp64_variant():
+    # Accuracy bound of the bit-exact variant against the FP64 variant after
+    # 1000 passes of the 4096-value pool.
+    x = oracle.Gen(42, 4, 1024).fill(4096 * 1000)
+    y = oracle.Gen64(42, 4, 1024).fill(4096 * 1000)
+    e = np.abs(x.astype(np.float64) - y) / np.maximum(1.0, np.abs(y))
+    assert e.max() <= 1e-5
+    assert math.sqrt((e ** 2).mean()) < 3e-6
+
+
+@pytest.mark.parametrize("mode", [oracle.SUM_F32, oracle.SUM_F32_COMP])
+def test_fp32_sum_modes_close_to_fp64(mode):
+    a = oracle.Gen(5, 16, 256, sum_mode=mode).fill(4096 * 50)
+    b = oracle.Gen(5, 16, 256).fill(4096 * 50)
+    assert np.max(np.abs(a - b)) < 1e-4
+
+
+def test_n16_sign_draws_and_composition():
+    # n = 16: the column signs come from bit 62 of each component's draw, and
+    # the generator applies them (H16 D / 4).
+    n, N = 16, 32
+    g = oracle.Gen(5, n, N)
+    X, sigma = g.pool, g.sigma
+    s = (5 + n * N * 0x9E3779B97F4A7C15) % (1 << 64)
+    seen = set()
+    for p in range(1, 6):
+        t = s
+        expect_signs = 0
+        for k in range(n):
+            t, w = oracle.splitmix64(t)
+            expect_signs |= ((w >> 62) & 1) << k
+        a, b, signs, s = oracle.pass_params(s, n, N)
+        assert signs == expect_signs
+        seen.add(signs)
+        c32, _, _ = oracle.scale32(float(X[-1]), sigma, n * N)
+        X = oracle.pass32(n, N, 0, a, b, np.float32(c32 * np.float32(0.25)), X, signs)
+        sigma = oracle.sumsq_f64(X)
+        g.do_pass()
+        assert np.array_equal(g.pool, X)
+    assert len(seen) == 5
+
+
+def test_fixed_h16_conserves_pool_total_every_second_pass():
+    # Why n = 16 draws column signs: with the same H16/4 every pass the pool
+    # total T obeys T'' = c c' T (the all-ones row of H16), so the output
+    # mean cannot average out. Random column signs break the recurrence.
+    n, N = 16, 64
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal(n * N).astype(np.float32)
+    a = np.array([3] * n, dtype=np.uint32)
+    T0 = float(X.astype(np.float64).sum())
+    Y = X
+    for _ in range(2):
+        b = rng.integers(0, N, size=n).astype(np.uint32)
+        Y = oracle.pass32(n, N, 0, a, b, np.float32(0.25), Y, 0)
+    assert abs(float(Y.astype(np.float64).sum()) - T0) < 1e-3
+    Z = X
+    for signs in (0x1234, 0x8421):
+        b = rng.integers(0, N, size=n).astype(np.uint32)
+        Z = oracle.pass32(n, N, 0, a, b, np.float32(0.25), Z, signs)
+    assert abs(float(Z.astype(np.float64).sum()) - T0) > 1.0
+
+
+def test_oracle_matches_frozen_stream_heads():
+    # Regression guard: any change to the oracle's arithmetic must be made on
+    # purpose (tests/golden/make_golden.py rewrites the file).
+    g = _golden("oracle_stream_heads.json")
+    for case in g["cases"]:
+        gen = oracle.Gen(case["seed"], case["n"], case["N"])
+        nu = case["n"] * case["N"]
+        x = gen.fill(nu * case["passes"])
+        assert [f"{int(v):08x}" for v in x[:32].view(np.uint32)] == case["head_bits"]
+        assert [f"{int(v):08x}" for v in x[-32:].view(np.uint32)] == case["tail_bits"]
+        assert float(gen.sigma).hex() == case["sigma_hex"]
+        assert str(gen.rng) == case["rng"]

@@ -1,0 +1,203 @@
+/*
+ * wallace.h -- C ABI of an MI355X (gfx950) implementation of Wallace's
+ * normal pseudo-random generator as described in R. P. Brent, "A fast
+ * vectorised implementation of Wallace's normal random number generator"
+ * (1997).
+ *
+ * The generator keeps a pool of nu = n*N normal variates, stored as n arrays
+ * of length N. One "pass" (section 2, eq. 1) regenerates the whole pool:
+ *
+ *     x'_k[j] = c * sum_i A[k][i] x_i[(a_i j + b_i) mod N],   j = 0..N-1,
+ *
+ * with odd strides a_i and offsets b_i drawn once per pass (eq. 2, sections
+ * 3 and 8), an orthogonal n x n matrix A (n = 4: alternately H4/2 and
+ * J/2 - I; n = 16: H16 D/4 with random column signs D), and a scale c that
+ * gives the new pool a chi-squared sum of squares (section 4, eq. 3).
+ * The output stream is the sequence of pools, each in flat order
+ * f = k*N + j (section 3).
+ *
+ * Every pass runs in HIP kernels on the GPU. Memory is owned by the caller:
+ * the library never allocates device memory. A generator's entire mutable
+ * device state lives in a caller-provided workspace that must be preserved
+ * between calls (section 8: RANN4's work area). The library allocates only a
+ * small host handle (freed by the matching destroy call).
+ *
+ * Conventions for every entry point:
+ *   - returns WALLACE_OK (0) or a negative WALLACE_E* code;
+ *   - argument errors are detected on the host BEFORE anything is enqueued,
+ *     and leave the generator unchanged;
+ *   - `stream` is a hipStream_t (NULL = the default stream); work is enqueued
+ *     on it and the call returns without synchronising, unless the comment
+ *     says otherwise;
+ *   - device pointers must come from hipMalloc (or a caching allocator on top
+ *     of it) on the current device; host pointers are plain host memory;
+ *   - a handle is not re-entrant: calls on one handle must be ordered (same
+ *     stream or external synchronisation). Two handles must not share a
+ *     workspace.
+ */
+#ifndef WALLACE_H
+#define WALLACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------- */
+#define WALLACE_OK 0
+#define WALLACE_EINVAL (-1)   /* bad argument (shape, pointer, option)       */
+#define WALLACE_ENOSPC (-2)   /* workspace smaller than required             */
+#define WALLACE_EHIP (-3)     /* a HIP runtime call failed                   */
+#define WALLACE_ECORRUPT (-4) /* workspace check failed (section 8 footnote) */
+#define WALLACE_EUNSUP (-5)   /* valid but unsupported combination           */
+#define WALLACE_ESTATE (-6)   /* call not valid in the handle's state        */
+
+/* Device flag bits reported by wallace_status / wallace_batch_status. */
+#define WALLACE_FLAG_CORRUPT 1u  /* sum of squares of the pool != stored value */
+#define WALLACE_FLAG_NONFINITE 2u /* scale factor not finite (pool destroyed)  */
+
+/* ---- options ----------------------------------------------------------------
+ * Zero-initialise and call wallace_default_opts, then change fields. */
+typedef struct wallace_opts {
+    int32_t f;               /* throw-away factor f >= 1 (section 6): only the
+                                pool after every f-th pass is returned          */
+    int32_t a_mode;          /* 0: strides from fixed prime pairs per component
+                                (section 8: alpha in {3,5}, beta in {7,11}, ...);
+                                1: any odd stride (eq. 2)                        */
+    int32_t reduce_mode;     /* sum of squares (section 4): 0 = FP64 pairwise
+                                tree (default), 1 = FP32 pairwise tree,
+                                2 = FP32 pairwise tree with error terms        */
+    int32_t transform_mode;  /* 0 = add/sub butterflies (bit-exact, default);
+                                1 = matrix cores (n = 16 only, not bit-exact)   */
+    int32_t withhold_driver; /* 1: do not return the pool value used to draw
+                                the chi-squared sum (section 4)                 */
+    int32_t check_workspace; /* 1: recompute the pool's sum of squares at the
+                                start of every call and flag a mismatch
+                                (section 8: a large change means the work area
+                                was overwritten)                               */
+} wallace_opts;
+
+/* Fills *opts with the defaults: f = 1, prime-pair strides, FP64 sum of
+ * squares, butterflies, emit the whole pool, no workspace check. */
+void wallace_default_opts(wallace_opts *opts);
+
+/* Human-readable text for a status code (static storage). */
+const char *wallace_strerror(int32_t code);
+
+/* ---- single generator ------------------------------------------------------ */
+
+typedef struct wallace_gen wallace_gen;
+
+/* Workspace bytes needed by one generator with n components (4 or 16) and
+ * N tuples (a power of two, N >= n). opts may be NULL.
+ * Section 8: the pool occupies about half of the work area in RANN4; here
+ * the pool needs 4*n*N bytes, plus a second pool buffer and reduction space
+ * when the pool is too large to stay on chip. */
+int32_t wallace_workspace_bytes(int32_t n, uint32_t N, const wallace_opts *opts,
+                                size_t *bytes);
+
+/* Creates a generator. Initial pool (section 5): n*N uniforms from splitmix64
+ * seeded with `seed`, Box-Muller in FP64 on the host, rounded to FP32, copied
+ * into d_workspace (256-byte aligned, >= wallace_workspace_bytes). The
+ * initial pool itself is not part of the output. Synchronises `stream`
+ * before returning. */
+int32_t wallace_init(uint64_t seed, int32_t n, uint32_t N,
+                     const wallace_opts *opts, void *d_workspace,
+                     size_t workspace_bytes, void *stream, wallace_gen **out);
+
+/* The initial pool that wallace_init uploads (section 5), computed on the
+ * host into host_pool (n*N floats, flat order); *rng_after receives the
+ * splitmix64 state after the n*N draws (may be NULL). Needs no GPU. */
+int32_t wallace_initial_pool(uint64_t seed, int32_t n, uint32_t N,
+                             float *host_pool, uint64_t *rng_after);
+
+/* Writes the next `count` values of the generator's output stream to d_out
+ * (device, 4-byte aligned, `count` floats). Any count >= 0 is allowed; the
+ * stream does not depend on how it is split over calls (section 8: the size
+ * of the returned array can vary from call to call). */
+int32_t wallace_fill(wallace_gen *g, float *d_out, uint64_t count, void *stream);
+
+/* Same as wallace_fill, then the affine map out = mu + sigma*x (one FP32
+ * multiply then one FP32 add) for N(mu, sigma^2) output (section 7). */
+int32_t wallace_fill_normal(wallace_gen *g, float *d_out, uint64_t count,
+                            float mu, float sigma, void *stream);
+
+/* Reads the current pool's sum of squares (as used for the next pass's
+ * scale) and the number of passes done. Synchronises `stream`. */
+int32_t wallace_sumsq(wallace_gen *g, double *sigma, uint64_t *passes,
+                      void *stream);
+
+/* Copies the current pool (n*N floats, flat order) to host memory.
+ * Synchronises `stream`. */
+int32_t wallace_read_pool(wallace_gen *g, float *host_pool, void *stream);
+
+/* Device flags (WALLACE_FLAG_*) accumulated since init; returns
+ * WALLACE_ECORRUPT if the corruption flag is set. Synchronises `stream`. */
+int32_t wallace_status(wallace_gen *g, uint32_t *flags, void *stream);
+
+/* Frees the host handle (not the workspace). NULL is a no-op. */
+int32_t wallace_destroy(wallace_gen *g);
+
+/* ---- many independent generators --------------------------------------------
+ * Section 9: independent streams need no communication after initialisation.
+ * A batch holds G generators, each with its own seed, n_g and N_g, in one
+ * workspace. Batched calls always run whole pools. */
+
+typedef struct wallace_batch wallace_batch;
+
+/* Workspace bytes for G generators with shapes n[g], N[g] (host arrays). */
+int32_t wallace_batch_workspace_bytes(uint32_t G, const int32_t *n,
+                                      const uint32_t *N, size_t *bytes);
+
+/* Initialises G generators (host arrays seeds, n, N; opts may be NULL and
+ * applies to all; f must be 1 and withhold_driver 0 in a batch). Box-Muller
+ * runs on the host on all cores. Synchronises `stream`. */
+int32_t wallace_batch_init(uint32_t G, const uint64_t *seeds, const int32_t *n,
+                           const uint32_t *N, const wallace_opts *opts,
+                           void *d_workspace, size_t workspace_bytes,
+                           void *stream, wallace_batch **out);
+
+/* Plans the next fills: generator g will run passes[g] passes and write
+ * passes[g]*n[g]*N[g] floats starting at element offsets[g] of the d_out
+ * given to wallace_fill_batched (pass-major, flat order within a pass).
+ * Regions must not overlap. Host arrays. Builds the work list (largest jobs
+ * first) with the schedule from the tuner (or defaults), copies it into the
+ * workspace and synchronises `stream`. */
+int32_t wallace_batch_plan(wallace_batch *b, const uint64_t *offsets,
+                           const uint32_t *passes, void *stream);
+
+/* Runs the planned passes for all generators in one persistent launch.
+ * Allocates nothing, copies nothing from the host and never synchronises, so
+ * it can be captured into a HIP graph; every call advances every generator.
+ * d_out must be 16-byte aligned. */
+int32_t wallace_fill_batched(wallace_batch *b, float *d_out, void *stream);
+
+/* Autotuner: for every (n, N) class in the batch, times each candidate
+ * schedule (lanes per pool, components per on-chip stage) on copies of the
+ * class's first generator in d_scratch (>= wallace_batch_tune_bytes), keeps
+ * the fastest and records it in the tuning cache file named by the
+ * environment variable WALLACE_TUNE_CACHE (if set). The generators' state is
+ * not touched. All candidates give bit-identical output. Synchronises.
+ * The environment variable WALLACE_SCHED="n:N:T:L:C,..." (read at every
+ * wallace_batch_init) forces the schedule of a class: L lanes per pool, T
+ * tuples per lane (T*L = N), C components per on-chip stage. */
+int32_t wallace_batch_tune_bytes(wallace_batch *b, size_t *bytes);
+int32_t wallace_batch_tune(wallace_batch *b, void *d_scratch,
+                           size_t scratch_bytes, void *stream);
+
+/* Per-generator sum of squares and passes done; synchronises. */
+int32_t wallace_batch_sumsq(wallace_batch *b, uint32_t g, double *sigma,
+                            uint64_t *passes, void *stream);
+
+/* OR of the device flags of all generators; synchronises. */
+int32_t wallace_batch_status(wallace_batch *b, uint32_t *flags, void *stream);
+
+/* Frees the host handle. NULL is a no-op. */
+int32_t wallace_batch_destroy(wallace_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WALLACE_H */

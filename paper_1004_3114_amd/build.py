@@ -1,0 +1,82 @@
+"""Build libwallace.so (HIP kernels for gfx950 + C++ host runtime) in-tree.
+
+Usage: python -m paper_1004_3114_amd.build   (or build() from Python)
+
+Flags that are part of the numerical contract:
+  -ffp-contract=off            no fused multiply-add contraction: the pass and
+                               the sum of squares are bit-exact only with the
+                               stated operation order
+  -fno-gpu-flush-denormals-to-zero   IEEE subnormals
+  -Xclang -target-feature -Xclang -packed-fp32-ops
+                               no packed FP32 (v_pk_*) instructions
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(PKG, "_build")
+LIBRARY = os.path.join(PKG, "libwallace.so")
+
+SOURCES = ["wallace_kernels.hip", "wallace_stream.hip", "wallace_host.cpp",
+           "wallace_batch.cpp", "wallace_tune.cpp"]
+
+ARCH = os.environ.get("WALLACE_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def common_flags():
+    return ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
+            f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function"]
+
+
+def compile_one(src: str) -> str:
+    path = os.path.join(CSRC, src)
+    obj = os.path.join(BUILD, src + ".o")
+    cmd = [hipcc(), *common_flags(), "-c", path, "-o", obj]
+    if src.endswith(".hip"):
+        cmd[1:1] = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
+                    "-Xclang", "-packed-fp32-ops", "-fno-gpu-flush-denormals-to-zero",
+                    "-x", "hip"]
+    else:
+        rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+        cmd[1:1] = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", f"-I{rocm}/include"]
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{proc.stdout}\n{proc.stderr}")
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source and link libwallace.so (always rebuilds)."""
+    os.makedirs(BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
+    tmp = LIBRARY + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           "-lpthread"]
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{proc.stdout}\n{proc.stderr}")
+    os.replace(tmp, LIBRARY)
+    if verbose:
+        print(f"built {LIBRARY}")
+    return LIBRARY
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,367 @@
+// Batches of independent generators (section 9: independent streams need no
+// communication after initialisation). All pools of a batch live in one
+// caller-provided workspace; a planned fill runs every generator's passes in
+// persistent pool-resident launches (one per (n, N) class).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <thread>
+#include <utility>
+#include <vector>
+
+#include "wallace.h"
+#include "wallace_internal.h"
+#include "wallace_runtime.h"
+#include "wallace_tune.h"
+
+using namespace wallace;
+
+namespace {
+
+struct BatchLayout {
+    size_t states, pools, jobs, total;
+    std::vector<uint64_t> pool_off;  // element offsets, 64-float aligned
+};
+
+BatchLayout batch_layout(uint32_t G, const int32_t *n, const uint32_t *N)
+{
+    BatchLayout L;
+    size_t off = sizeof(WsHeader);
+    L.states = off;
+    off = align_up(off + (size_t)G * sizeof(GenState), kAlign);
+    L.pools = off;
+    L.pool_off.resize(G);
+    uint64_t el = 0;
+    for (uint32_t g = 0; g < G; ++g) {
+        L.pool_off[g] = el;
+        el += align_up((size_t)n[g] * N[g], 64);
+    }
+    off = align_up(off + el * sizeof(float), kAlign);
+    L.jobs = off;
+    off = align_up(off + (size_t)G * sizeof(Job), kAlign);
+    L.total = off;
+    return L;
+}
+
+struct ClassInfo {
+    int n;
+    uint32_t N;
+    Sched sched;
+    std::vector<uint32_t> gens;  // generators of this class
+    uint32_t job_begin = 0, job_count = 0;
+    int grid = 0;
+};
+
+}  // namespace
+
+struct wallace_batch {
+    uint32_t G;
+    std::vector<int32_t> n;
+    std::vector<uint32_t> N;
+    wallace_opts opts;
+    char *ws;
+    BatchLayout lay;
+    std::vector<ClassInfo> classes;
+    bool planned = false;
+    int cus = 0;
+};
+
+namespace {
+
+hipError_t class_grid(ClassInfo &c, int cus, uint32_t rmode)
+{
+    int per_cu = 0;
+    hipError_t e = pool_max_blocks_per_cu(c.sched, (int)c.N, rmode, &per_cu);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    const int gpb = c.sched.L > 64 ? 1 : 256 / c.sched.L;
+    const uint64_t need = (c.job_count + (uint32_t)gpb - 1) / (uint32_t)gpb;
+    const uint64_t resident = (uint64_t)per_cu * (uint64_t)cus;
+    c.grid = (int)std::max<uint64_t>(1, std::min(need, resident));
+    return hipSuccess;
+}
+
+PoolArgs class_args(const wallace_batch *b, const ClassInfo &c, float *out,
+                    uint32_t sigma_mode)
+{
+    PoolArgs a{};
+    a.jobs = reinterpret_cast<const Job *>(b->ws + b->lay.jobs) + c.job_begin;
+    a.njobs = c.job_count;
+    a.f = 1;
+    a.emit_len = (uint32_t)((uint64_t)c.n * c.N);
+    a.a_mode = (uint32_t)b->opts.a_mode;
+    a.rmode = (uint32_t)b->opts.reduce_mode;
+    a.sigma_mode = sigma_mode;
+    a.out = out;
+    a.pools = reinterpret_cast<float *>(b->ws + b->lay.pools);
+    a.states = reinterpret_cast<GenState *>(b->ws + b->lay.states);
+    a.r_nu = chi2_root((uint64_t)c.n * c.N);
+    a.N = (int)c.N;
+    a.L = c.sched.L;
+    a.logL = ilog2((uint64_t)c.sched.L);
+    a.C = c.sched.C;
+    a.groups_per_block = c.sched.L > 64 ? 1 : 256 / c.sched.L;
+    return a;
+}
+
+// Uploads jobs for every class (class-major order) and sets job ranges.
+hipError_t upload_jobs(wallace_batch *b, const std::vector<Job> &jobs, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(b->ws + b->lay.jobs, jobs.data(), jobs.size() * sizeof(Job),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+hipError_t launch_classes(wallace_batch *b, float *out, uint32_t sigma_mode, hipStream_t s)
+{
+    for (const ClassInfo &c : b->classes) {
+        if (c.job_count == 0) continue;
+        const PoolArgs a = class_args(b, c, out, sigma_mode);
+        hipError_t e = launch_pool(c.sched, a, c.grid, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t wallace_batch_workspace_bytes(uint32_t G, const int32_t *n, const uint32_t *N,
+                                      size_t *bytes)
+{
+    if (!bytes || !n || !N || G == 0) return WALLACE_EINVAL;
+    for (uint32_t g = 0; g < G; ++g) {
+        Sched s;
+        if (!shape_ok(n[g], N[g])) return WALLACE_EINVAL;
+        if (!default_sched(n[g], N[g], &s)) return WALLACE_EUNSUP;
+    }
+    *bytes = batch_layout(G, n, N).total;
+    return WALLACE_OK;
+}
+
+int32_t wallace_batch_init(uint32_t G, const uint64_t *seeds, const int32_t *n,
+                           const uint32_t *N, const wallace_opts *opts, void *d_workspace,
+                           size_t workspace_bytes, void *stream, wallace_batch **out)
+{
+    if (!out || !seeds || !n || !N || !d_workspace || G == 0) return WALLACE_EINVAL;
+    *out = nullptr;
+    wallace_opts o;
+    wallace_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.f != 1 || o.withhold_driver != 0 || o.transform_mode != 0) return WALLACE_EUNSUP;
+    if (o.a_mode < 0 || o.a_mode > 1 || o.reduce_mode < 0 || o.reduce_mode > 2 ||
+        o.check_workspace < 0 || o.check_workspace > 1)
+        return WALLACE_EINVAL;
+    if (((uintptr_t)d_workspace) & (kAlign - 1)) return WALLACE_EINVAL;
+    size_t need = 0;
+    int32_t rc = wallace_batch_workspace_bytes(G, n, N, &need);
+    if (rc != WALLACE_OK) return rc;
+    if (workspace_bytes < need) return WALLACE_ENOSPC;
+
+    wallace_batch *b = new (std::nothrow) wallace_batch();
+    if (!b) return WALLACE_EINVAL;
+    b->G = G;
+    b->n.assign(n, n + G);
+    b->N.assign(N, N + G);
+    b->opts = o;
+    b->ws = static_cast<char *>(d_workspace);
+    b->lay = batch_layout(G, n, N);
+    if (num_cus(&b->cus) != hipSuccess) {
+        delete b;
+        return WALLACE_EHIP;
+    }
+
+    // classes by shape, with the tuned (or default) schedule
+    std::map<std::pair<int, uint32_t>, size_t> index;
+    for (uint32_t g = 0; g < G; ++g) {
+        auto key = std::make_pair((int)n[g], N[g]);
+        auto it = index.find(key);
+        if (it == index.end()) {
+            ClassInfo c;
+            c.n = n[g];
+            c.N = N[g];
+            if (!tuned_sched(c.n, c.N, &c.sched)) default_sched(c.n, c.N, &c.sched);
+            index[key] = b->classes.size();
+            b->classes.push_back(c);
+            it = index.find(key);
+        }
+        b->classes[it->second].gens.push_back(g);
+    }
+
+    // initial pools on all host cores (section 5)
+    uint64_t total_el = 0;
+    for (uint32_t g = 0; g < G; ++g) total_el = std::max<uint64_t>(total_el, b->lay.pool_off[g] + (uint64_t)n[g] * N[g]);
+    std::vector<float> host(total_el, 0.0f);
+    std::vector<GenState> st(G);
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nth; ++t) {
+        th.emplace_back([&, t]() {
+            for (uint32_t g = t; g < G; g += nth) {
+                st[g] = GenState{};
+                host_box_muller(seeds[g], (size_t)n[g] * N[g], host.data() + b->lay.pool_off[g],
+                                &st[g].rng);
+            }
+        });
+    }
+    for (auto &x : th) x.join();
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    WsHeader hdr{};
+    hdr.magic = kWsMagic;
+    hdr.G = G;
+    hipError_t e = hipMemcpyAsync(b->ws, &hdr, sizeof(hdr), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + b->lay.states, st.data(), G * sizeof(GenState),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + b->lay.pools, host.data(), total_el * sizeof(float),
+                           hipMemcpyHostToDevice, s);
+    // sum of squares of every initial pool, by the pass kernels' own tree
+    std::vector<Job> jobs;
+    jobs.reserve(G);
+    for (ClassInfo &c : b->classes) {
+        c.job_begin = (uint32_t)jobs.size();
+        for (uint32_t g : c.gens) {
+            Job j{};
+            j.pool_off = b->lay.pool_off[g];
+            j.gen = g;
+            jobs.push_back(j);
+        }
+        c.job_count = (uint32_t)c.gens.size();
+        if (e == hipSuccess) e = class_grid(c, b->cus, (uint32_t)b->opts.reduce_mode);
+    }
+    if (e == hipSuccess) e = upload_jobs(b, jobs, s);
+    if (e == hipSuccess) e = launch_classes(b, nullptr, 2, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete b;
+        return WALLACE_EHIP;
+    }
+    *out = b;
+    return WALLACE_OK;
+}
+
+int32_t wallace_batch_plan(wallace_batch *b, const uint64_t *offsets, const uint32_t *passes,
+                           void *stream)
+{
+    if (!b || !offsets || !passes) return WALLACE_EINVAL;
+    // regions must not overlap
+    std::vector<std::pair<uint64_t, uint64_t>> reg;
+    reg.reserve(b->G);
+    for (uint32_t g = 0; g < b->G; ++g) {
+        const uint64_t len = (uint64_t)passes[g] * b->n[g] * b->N[g];
+        if (passes[g] && len / passes[g] != (uint64_t)b->n[g] * b->N[g]) return WALLACE_EINVAL;
+        if (len) reg.emplace_back(offsets[g], offsets[g] + len);
+    }
+    std::sort(reg.begin(), reg.end());
+    for (size_t i = 1; i < reg.size(); ++i)
+        if (reg[i].first < reg[i - 1].second) return WALLACE_EINVAL;
+
+    std::vector<Job> jobs;
+    jobs.reserve(b->G);
+    for (ClassInfo &c : b->classes) {
+        c.job_begin = (uint32_t)jobs.size();
+        std::vector<uint32_t> order = c.gens;
+        // largest jobs first: with static round-robin assignment this keeps
+        // the long chains from landing last
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t x, uint32_t y) { return passes[x] > passes[y]; });
+        for (uint32_t g : order) {
+            Job j{};
+            j.out_off = offsets[g];
+            j.pool_off = b->lay.pool_off[g];
+            j.gen = g;
+            j.passes = passes[g];
+            j.last_emit = (uint32_t)((uint64_t)b->n[g] * b->N[g]);
+            jobs.push_back(j);
+        }
+        c.job_count = (uint32_t)order.size();
+        if (class_grid(c, b->cus, (uint32_t)b->opts.reduce_mode) != hipSuccess) return WALLACE_EHIP;
+    }
+    if (upload_jobs(b, jobs, static_cast<hipStream_t>(stream)) != hipSuccess) return WALLACE_EHIP;
+    b->planned = true;
+    return WALLACE_OK;
+}
+
+int32_t wallace_fill_batched(wallace_batch *b, float *d_out, void *stream)
+{
+    if (!b || !d_out || (((uintptr_t)d_out) & 15)) return WALLACE_EINVAL;
+    if (!b->planned) return WALLACE_ESTATE;
+    const uint32_t sm = b->opts.check_workspace ? 1u : 0u;
+    if (launch_classes(b, d_out, sm, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return WALLACE_EHIP;
+    return WALLACE_OK;
+}
+
+int32_t wallace_batch_sumsq(wallace_batch *b, uint32_t g, double *sigma, uint64_t *passes,
+                            void *stream)
+{
+    if (!b || g >= b->G) return WALLACE_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GenState st;
+    const GenState *src = reinterpret_cast<const GenState *>(b->ws + b->lay.states) + g;
+    if (hipMemcpyAsync(&st, src, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return WALLACE_EHIP;
+    if (sigma) *sigma = st.sigma;
+    if (passes) *passes = st.passes;
+    return WALLACE_OK;
+}
+
+int32_t wallace_batch_status(wallace_batch *b, uint32_t *flags, void *stream)
+{
+    if (!b) return WALLACE_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<GenState> st(b->G);
+    if (hipMemcpyAsync(st.data(), b->ws + b->lay.states, b->G * sizeof(GenState),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return WALLACE_EHIP;
+    uint32_t f = 0;
+    for (const GenState &x : st) f |= x.flags;
+    if (flags) *flags = f;
+    return (f & WALLACE_FLAG_CORRUPT) ? WALLACE_ECORRUPT : WALLACE_OK;
+}
+
+int32_t wallace_batch_destroy(wallace_batch *b)
+{
+    delete b;
+    return WALLACE_OK;
+}
+
+int32_t wallace_batch_tune_bytes(wallace_batch *b, size_t *bytes)
+{
+    if (!b || !bytes) return WALLACE_EINVAL;
+    size_t m = 0;
+    for (const ClassInfo &c : b->classes) m = std::max(m, tune_scratch_bytes(c.n, c.N));
+    *bytes = m;
+    return WALLACE_OK;
+}
+
+int32_t wallace_batch_tune(wallace_batch *b, void *d_scratch, size_t scratch_bytes,
+                           void *stream)
+{
+    if (!b || !d_scratch || (((uintptr_t)d_scratch) & (kAlign - 1))) return WALLACE_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (ClassInfo &c : b->classes) {
+        if (scratch_bytes < tune_scratch_bytes(c.n, c.N)) return WALLACE_ENOSPC;
+        const GenState *st = reinterpret_cast<const GenState *>(b->ws + b->lay.states) + c.gens[0];
+        const float *pool = reinterpret_cast<const float *>(b->ws + b->lay.pools) +
+                            b->lay.pool_off[c.gens[0]];
+        Sched best;
+        int32_t rc = tune_class(c.n, c.N, b->opts, st, pool, static_cast<char *>(d_scratch),
+                                (uint32_t)std::min<size_t>(c.gens.size(), 4096), b->cus, s, &best);
+        if (rc != WALLACE_OK) return rc;
+        c.sched = best;
+    }
+    b->planned = false;  // grids depend on the schedule: plan again
+    return WALLACE_OK;
+}
+
+}  // extern "C"

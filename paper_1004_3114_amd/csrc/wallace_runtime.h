@@ -1,0 +1,61 @@
+// Internal interfaces between the host runtime pieces of the Wallace
+// generator library (single generators, streaming large pools, batches).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "wallace.h"
+#include "wallace_internal.h"
+
+namespace wallace {
+
+uint64_t host_splitmix_next(uint64_t &s);
+void host_box_muller(uint64_t seed, size_t nu, float *pool, uint64_t *rng_after);
+bool pow2(uint64_t x);
+int ilog2(uint64_t x);
+bool shape_ok(int n, uint32_t N);
+bool default_sched(int n, uint32_t N, Sched *out);
+hipError_t num_cus(int *cus);
+double chi2_root(uint64_t nu);
+
+// Byte offsets of a single generator's workspace regions.
+struct Layout {
+    size_t state, pool, pool2, partials, scratch, total;
+};
+
+}  // namespace wallace
+
+// Host handle of one generator. The device state lives in the workspace;
+// the host keeps only what is decided on the host (shape, options, how much
+// of the current pool has been returned, passes enqueued).
+struct wallace_gen {
+    int n;
+    uint32_t N;
+    uint64_t nu;
+    wallace_opts opts;
+    char *ws;
+    wallace::Layout lay;
+    wallace::GenState *state;
+    float *pool;
+    uint64_t emit_len;
+    uint64_t cursor;       // values of the current returned pool already emitted
+    uint64_t passes_host;  // passes enqueued since init (ping-pong parity)
+    bool streaming;
+    wallace::Sched sched;
+    double r_nu;
+};
+
+namespace wallace {
+
+// Streaming path for pools too large to stay on chip (wallace_stream.hip).
+size_t stream_partials_bytes(int n, uint32_t N);
+bool stream_shape_ok(int n, uint32_t N);
+const float *stream_current_pool(wallace_gen *g);
+hipError_t stream_check(wallace_gen *g, hipStream_t s);
+hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last_emit,
+                      uint32_t affine, float mu, float sig, hipStream_t s);
+
+}  // namespace wallace

@@ -1,0 +1,181 @@
+"""GPU parity of batched generators (independent pools, section 9) against
+the FP32 oracle, including the full-size uniform and uneven workloads in the
+launch configuration the benchmark times (sampled generators)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+from paper_1004_3114_amd import wallace as W  # noqa: E402
+from paper_1004_3114_amd import workloads  # noqa: E402
+from tests.test_gpu_parity import assert_bits_equal  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def oracle_generator_output(seed, n, N, passes):
+    return oracle.Gen(int(seed), int(n), int(N)).fill(int(n) * int(N) * int(passes))
+
+
+def test_mixed_small_batch_two_launches():
+    _dev()
+    rng = np.random.default_rng(1)
+    shapes = [(4, 4), (4, 64), (4, 256), (4, 1024), (4, 4096), (4, 16384), (16, 16),
+              (16, 64), (16, 256), (16, 1024), (16, 4096)]
+    G = 40
+    pick = rng.integers(0, len(shapes), size=G)
+    n = np.array([shapes[i][0] for i in pick], dtype=np.int32)
+    N = np.array([shapes[i][1] for i in pick], dtype=np.uint32)
+    seeds = np.arange(500, 500 + G, dtype=np.uint64)
+    passes = rng.integers(0, 9, size=G).astype(np.uint32)
+    nu = n.astype(np.uint64) * N
+    sizes = nu * passes
+    off = np.zeros(G, np.uint64)
+    np.cumsum(sizes[:-1], out=off[1:])
+    total = int(sizes.sum())
+    print(f"case mixed batch G={G} total={total}", flush=True)
+    b = W.Batch(seeds, n, N)
+    b.plan(off, passes)
+    outs = []
+    for launch in range(2):
+        out = torch.full((max(total, 1),), float("nan"), dtype=torch.float32, device="cuda")
+        b.fill(out)
+        outs.append(out.cpu().numpy())
+    for g in range(G):
+        ref = oracle_generator_output(seeds[g], n[g], N[g], 2 * int(passes[g]))
+        L = int(sizes[g])
+        got = np.concatenate([o[int(off[g]):int(off[g]) + L] for o in outs])
+        assert_bits_equal(got, ref, f"gen {g} n={n[g]} N={N[g]} passes={passes[g]}")
+        s, p = b.sumsq(g)
+        assert p == 2 * passes[g]
+    assert b.status() == (0, 0)
+
+
+@pytest.mark.parametrize("n,N", [(4, 256), (4, 2048), (16, 64), (16, 1024), (4, 16384)])
+def test_every_schedule_gives_identical_bits(n, N, monkeypatch):
+    # Schedules differ in lanes per pool, tuples per lane and components per
+    # LDS stage; the tree order of every reduction is the same, so each one
+    # must reproduce the oracle exactly.
+    _dev()
+    cands = []
+    for T in (1, 2, 4, 8, 16):
+        if N % T or (n == 16 and T > 4):
+            continue
+        L = N // T
+        if L < n or L > 1024:
+            continue
+        for C in (n, n // 2):
+            if C * N * 4 > 128 * 1024 or (L <= 64 and C != n):
+                continue
+            cands.append((T, L, C))
+    assert cands
+    G = 9
+    seeds = np.arange(70, 70 + G, dtype=np.uint64)
+    passes = np.full(G, 3, dtype=np.uint32)
+    nu = n * N
+    off = np.arange(G, dtype=np.uint64) * (nu * 3)
+    refs = [oracle_generator_output(s, n, N, 3) for s in seeds]
+    for T, L, C in cands:
+        monkeypatch.setenv("WALLACE_SCHED", f"{n}:{N}:{T}:{L}:{C}")
+        print(f"case sched n={n} N={N} T={T} L={L} C={C}", flush=True)
+        b = W.Batch(seeds, [n] * G, [N] * G)
+        b.plan(off, passes)
+        out = torch.empty(G * nu * 3, dtype=torch.float32, device="cuda")
+        b.fill(out)
+        host = out.cpu().numpy()
+        for g in range(G):
+            assert_bits_equal(host[g * nu * 3:(g + 1) * nu * 3], refs[g],
+                              f"T={T} L={L} C={C} gen {g}")
+
+
+def test_tuner_runs_and_keeps_state(tmp_path, monkeypatch):
+    _dev()
+    monkeypatch.setenv("WALLACE_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    G = 64
+    seeds = np.arange(900, 900 + G, dtype=np.uint64)
+    n = np.array([4] * 32 + [16] * 32, dtype=np.int32)
+    N = np.array([1024] * 32 + [256] * 32, dtype=np.uint32)
+    b = W.Batch(seeds, n, N)
+    b.tune()
+    passes = np.full(G, 2, dtype=np.uint32)
+    nu = n.astype(np.uint64) * N
+    off = np.zeros(G, np.uint64)
+    np.cumsum((nu * 2)[:-1], out=off[1:])
+    b.plan(off, passes)
+    out = torch.empty(int((nu * 2).sum()), dtype=torch.float32, device="cuda")
+    b.fill(out)
+    host = out.cpu().numpy()
+    for g in (0, 31, 32, 63):
+        ref = oracle_generator_output(seeds[g], n[g], N[g], 2)
+        assert_bits_equal(host[int(off[g]):int(off[g]) + int(nu[g]) * 2], ref, f"gen {g}")
+    text = (tmp_path / "tune.txt").read_text().split("\n")
+    assert len([t for t in text if t.strip()]) == 2
+
+
+def test_batch_uniform_full_size_graph():
+    # 65,536 generators (n = 4, N = 256, seeds 42 + g), 64 passes per launch,
+    # 4 launches captured in one HIP graph, as the benchmark runs them.
+    _dev()
+    spec = workloads.batch_uniform()
+    per = spec.normals_per_launch()
+    print(f"case batch_uniform full size per launch {per}", flush=True)
+    b = W.Batch(spec.seeds, spec.n, spec.N)
+    off = spec.offsets()
+    b.plan(off, spec.passes)
+    out = torch.empty(per * spec.launches, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        for launch in range(spec.launches):
+            b.fill(out[launch * per:], stream=torch.cuda.current_stream())
+    graph.replay()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    sample = sorted(set([0, 1, 4095, 65535] + [int(x) for x in rng.integers(0, spec.G, 12)]))
+    nu = 1024
+    for g in sample:
+        ref = oracle_generator_output(spec.seeds[g], 4, 256, 64 * spec.launches)
+        got = np.concatenate([
+            out[launch * per + int(off[g]): launch * per + int(off[g]) + 64 * nu].cpu().numpy()
+            for launch in range(spec.launches)])
+        assert_bits_equal(got, ref, f"batch_uniform gen {g}")
+    s, p = b.sumsq(65535)
+    assert p == 256
+    del out
+    torch.cuda.empty_cache()
+
+
+def test_batch_uneven_full_size_sampled():
+    _dev()
+    spec = workloads.batch_uneven()
+    per = spec.normals_per_launch()
+    print(f"case batch_uneven full size {per}", flush=True)
+    b = W.Batch(spec.seeds, spec.n, spec.N)
+    off = spec.offsets()
+    b.plan(off, spec.passes)
+    out = torch.empty(per, dtype=torch.float32, device="cuda")
+    b.fill(out)
+    torch.cuda.synchronize()
+    picked = {}
+    for g in range(spec.G):
+        key = (int(spec.n[g]), int(spec.N[g]))
+        picked.setdefault(key, [])
+        if len(picked[key]) < 1 and spec.passes[g] <= 64:
+            picked[key].append(g)
+    picked[(-1, -1)] = [int(np.argmax(spec.nu * spec.passes))]  # the longest job
+    for key, gs in sorted(picked.items()):
+        for g in gs:
+            L = int(spec.nu[g]) * int(spec.passes[g])
+            ref = oracle_generator_output(spec.seeds[g], spec.n[g], spec.N[g], spec.passes[g])
+            got = out[int(off[g]):int(off[g]) + L].cpu().numpy()
+            assert_bits_equal(got, ref, f"uneven gen {g} n={spec.n[g]} N={spec.N[g]}")
+    del out
+    torch.cuda.empty_cache()

@@ -86,6 +86,10 @@ void wallace_default_opts(wallace_opts *opts);
 /* Human-readable text for a status code (static storage). */
 const char *wallace_strerror(int32_t code);
 
+/* Text of the last HIP runtime error behind a WALLACE_EHIP return in the
+ * calling thread (empty if none). Valid until the next call in the thread. */
+const char *wallace_last_error(void);
+
 /* ---- single generator ------------------------------------------------------ */
 
 typedef struct wallace_gen wallace_gen;

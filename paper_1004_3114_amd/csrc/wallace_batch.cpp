@@ -171,9 +171,10 @@ int32_t wallace_batch_init(uint32_t G, const uint64_t *seeds, const int32_t *n,
     b->opts = o;
     b->ws = static_cast<char *>(d_workspace);
     b->lay = batch_layout(G, n, N);
-    if (num_cus(&b->cus) != hipSuccess) {
+    hipError_t ec = num_cus(&b->cus);
+    if (ec != hipSuccess) {
         delete b;
-        return WALLACE_EHIP;
+        return hip_fail(ec, "device query");
     }
 
     // classes by shape, with the tuned (or default) schedule
@@ -241,7 +242,7 @@ int32_t wallace_batch_init(uint32_t G, const uint64_t *seeds, const int32_t *n,
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         delete b;
-        return WALLACE_EHIP;
+        return hip_fail(e, "wallace_batch_init");
     }
     *out = b;
     return WALLACE_OK;
@@ -282,9 +283,11 @@ int32_t wallace_batch_plan(wallace_batch *b, const uint64_t *offsets, const uint
             jobs.push_back(j);
         }
         c.job_count = (uint32_t)order.size();
-        if (class_grid(c, b->cus, (uint32_t)b->opts.reduce_mode) != hipSuccess) return WALLACE_EHIP;
+        hipError_t e = class_grid(c, b->cus, (uint32_t)b->opts.reduce_mode);
+        if (e != hipSuccess) return hip_fail(e, "occupancy query");
     }
-    if (upload_jobs(b, jobs, static_cast<hipStream_t>(stream)) != hipSuccess) return WALLACE_EHIP;
+    hipError_t e = upload_jobs(b, jobs, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "job upload");
     b->planned = true;
     return WALLACE_OK;
 }
@@ -294,8 +297,8 @@ int32_t wallace_fill_batched(wallace_batch *b, float *d_out, void *stream)
     if (!b || !d_out || (((uintptr_t)d_out) & 15)) return WALLACE_EINVAL;
     if (!b->planned) return WALLACE_ESTATE;
     const uint32_t sm = b->opts.check_workspace ? 1u : 0u;
-    if (launch_classes(b, d_out, sm, static_cast<hipStream_t>(stream)) != hipSuccess)
-        return WALLACE_EHIP;
+    hipError_t e = launch_classes(b, d_out, sm, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
     return WALLACE_OK;
 }
 
@@ -306,9 +309,9 @@ int32_t wallace_batch_sumsq(wallace_batch *b, uint32_t g, double *sigma, uint64_
     hipStream_t s = static_cast<hipStream_t>(stream);
     GenState st;
     const GenState *src = reinterpret_cast<const GenState *>(b->ws + b->lay.states) + g;
-    if (hipMemcpyAsync(&st, src, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return WALLACE_EHIP;
+    hipError_t e = hipMemcpyAsync(&st, src, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "wallace_batch_sumsq");
     if (sigma) *sigma = st.sigma;
     if (passes) *passes = st.passes;
     return WALLACE_OK;
@@ -319,10 +322,10 @@ int32_t wallace_batch_status(wallace_batch *b, uint32_t *flags, void *stream)
     if (!b) return WALLACE_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<GenState> st(b->G);
-    if (hipMemcpyAsync(st.data(), b->ws + b->lay.states, b->G * sizeof(GenState),
-                       hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return WALLACE_EHIP;
+    hipError_t e = hipMemcpyAsync(st.data(), b->ws + b->lay.states, b->G * sizeof(GenState),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "wallace_batch_status");
     uint32_t f = 0;
     for (const GenState &x : st) f |= x.flags;
     if (flags) *flags = f;

@@ -54,6 +54,17 @@ void host_box_muller(uint64_t seed, size_t nu, float *pool, uint64_t *rng_after)
     if (rng_after) *rng_after = s;
 }
 
+static thread_local char g_last_error[256];
+
+int32_t hip_fail(hipError_t e, const char *where)
+{
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where,
+                  hipGetErrorString(e), (int)e);
+    return WALLACE_EHIP;
+}
+
+const char *last_error_text() { return g_last_error; }
+
 bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
 int ilog2(uint64_t x)
@@ -161,6 +172,8 @@ void wallace_default_opts(wallace_opts *o)
     o->f = 1;
 }
 
+const char *wallace_last_error(void) { return last_error_text(); }
+
 const char *wallace_strerror(int32_t code)
 {
     switch (code) {
@@ -250,7 +263,7 @@ int32_t wallace_init(uint64_t seed, int32_t n, uint32_t N,
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         delete g;
-        return WALLACE_EHIP;
+        return hip_fail(e, "wallace_init");
     }
     *out = g;
     return WALLACE_OK;
@@ -274,12 +287,12 @@ static int32_t fill_impl(wallace_gen *g, float *d_out, uint64_t count,
     if (g->opts.check_workspace) {
         // pool-resident jobs check inside the pass kernel
         e = g->streaming ? stream_check(g, s) : hipSuccess;
-        if (e != hipSuccess) return WALLACE_EHIP;
+        if (e != hipSuccess) return hip_fail(e, "workspace check");
     }
     if (k0 > 0) {
         const float *cur = g->streaming ? stream_current_pool(g) : g->pool;
         e = launch_copy_head(d_out, cur + g->cursor, (uint32_t)k0, affine, mu, sig, s);
-        if (e != hipSuccess) return WALLACE_EHIP;
+        if (e != hipSuccess) return hip_fail(e, "copy head");
     }
     if (rem > 0) {
         const uint64_t tail = rem - (npools - 1) * len;
@@ -316,7 +329,7 @@ static int32_t fill_impl(wallace_gen *g, float *d_out, uint64_t count,
             a.groups_per_block = g->sched.L > 64 ? 1 : 256 / g->sched.L;
             e = launch_pool(g->sched, a, 1, s);
         }
-        if (e != hipSuccess) return WALLACE_EHIP;
+        if (e != hipSuccess) return hip_fail(e, "pass launch");
         g->cursor = tail;
         g->passes_host += passes;
     } else {
@@ -341,9 +354,9 @@ int32_t wallace_sumsq(wallace_gen *g, double *sigma, uint64_t *passes, void *str
     if (!g) return WALLACE_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     GenState st;
-    if (hipMemcpyAsync(&st, g->state, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return WALLACE_EHIP;
+    hipError_t e = hipMemcpyAsync(&st, g->state, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "wallace_sumsq");
     if (sigma) *sigma = st.sigma;
     if (passes) *passes = st.passes;
     return WALLACE_OK;
@@ -354,10 +367,9 @@ int32_t wallace_read_pool(wallace_gen *g, float *host_pool, void *stream)
     if (!g || !host_pool) return WALLACE_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const float *src = g->streaming ? stream_current_pool(g) : g->pool;
-    if (hipMemcpyAsync(host_pool, src, g->nu * sizeof(float), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return WALLACE_EHIP;
+    hipError_t e = hipMemcpyAsync(host_pool, src, g->nu * sizeof(float), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "wallace_read_pool");
     return WALLACE_OK;
 }
 
@@ -366,9 +378,9 @@ int32_t wallace_status(wallace_gen *g, uint32_t *flags, void *stream)
     if (!g) return WALLACE_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     GenState st;
-    if (hipMemcpyAsync(&st, g->state, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return WALLACE_EHIP;
+    hipError_t e = hipMemcpyAsync(&st, g->state, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "wallace_status");
     if (flags) *flags = st.flags;
     return (st.flags & WALLACE_FLAG_CORRUPT) ? WALLACE_ECORRUPT : WALLACE_OK;
 }

@@ -229,7 +229,7 @@ int32_t tune_class(int n, uint32_t N, const wallace_opts &opts, const GenState *
     }
     if (ev0) hipEventDestroy(ev0);
     if (ev1) hipEventDestroy(ev1);
-    if (e != hipSuccess) return WALLACE_EHIP;
+    if (e != hipSuccess) return hip_fail(e, "tuning run");
     *best = cand[best_i];
     std::lock_guard<std::mutex> lk(g_mu);
     load_cache_locked();

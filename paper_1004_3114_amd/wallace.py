@@ -32,7 +32,10 @@ FLAG_NONFINITE = 2
 
 class WallaceError(RuntimeError):
     def __init__(self, code: int, what: str):
-        super().__init__(f"{what}: {strerror(code)} ({code})")
+        detail = ""
+        if code == WALLACE_EHIP and _lib is not None:
+            detail = " [" + (_lib.wallace_last_error() or b"").decode() + "]"
+        super().__init__(f"{what}: {strerror(code)} ({code}){detail}")
         self.code = code
 
 
@@ -54,6 +57,7 @@ _f32 = ctypes.c_float
 SIGNATURES = {
     "wallace_default_opts": (None, [ctypes.POINTER(wallace_opts)]),
     "wallace_strerror": (ctypes.c_char_p, [_i32]),
+    "wallace_last_error": (ctypes.c_char_p, []),
     "wallace_workspace_bytes": (_i32, [_i32, _u32, ctypes.POINTER(wallace_opts),
                                        ctypes.POINTER(_sz)]),
     "wallace_init": (_i32, [_u64, _i32, _u32, ctypes.POINTER(wallace_opts), _vp, _sz,
@@ -88,6 +92,9 @@ def lib():
     if not os.path.exists(LIBRARY):
         raise ImportError(f"{LIBRARY} is missing: run paper_1004_3114_amd.build.build() "
                           "(the HIP library is required; there is no fallback)")
+    # torch first: the library and torch must share one HIP runtime in the
+    # process, and the first libamdhip64.so.7 loaded serves both
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIBRARY)
     for name, (rt, args) in SIGNATURES.items():
         fn = getattr(L, name)

@@ -25,8 +25,17 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIBRARY = os.path.join(PKG, "libwallace.so")
 
-SOURCES = ["wallace_kernels.hip", "wallace_stream.hip", "wallace_host.cpp",
-           "wallace_batch.cpp", "wallace_tune.cpp"]
+# (source, extra defines, object name)
+SOURCES = [("wallace_kernels.hip", [], "wallace_kernels"),
+           ("wallace_stream.hip", [], "wallace_stream"),
+           ("wallace_host.cpp", [], "wallace_host"),
+           ("wallace_batch.cpp", [], "wallace_batch"),
+           ("wallace_tune.cpp", [], "wallace_tune")]
+for _n in (4, 16):
+    for _rm in (0, 1, 2):
+        SOURCES.append(("wallace_pool_inst.hip",
+                        [f"-DWALLACE_POOL_N={_n}", f"-DWALLACE_POOL_RM={_rm}"],
+                        f"wallace_pool_{_n}_{_rm}"))
 
 ARCH = os.environ.get("WALLACE_OFFLOAD_ARCH", "gfx950")
 
@@ -43,10 +52,11 @@ def common_flags():
             f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function"]
 
 
-def compile_one(src: str) -> str:
+def compile_one(item) -> str:
+    src, defines, name = item
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, src + ".o")
-    cmd = [hipcc(), *common_flags(), "-c", path, "-o", obj]
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [hipcc(), *common_flags(), *defines, "-c", path, "-o", obj]
     if src.endswith(".hip"):
         cmd[1:1] = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
                     "-Xclang", "-packed-fp32-ops", "-fno-gpu-flush-denormals-to-zero",
@@ -63,7 +73,7 @@ def compile_one(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source and link libwallace.so (always rebuilds)."""
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIBRARY + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,

@@ -1,0 +1,703 @@
+// Pool-resident pass kernels of the Wallace generator library (gfx950).
+//
+// One pass (Brent 1997, section 2, eq. 1) regenerates a pool of nu = n*N
+// normals held as n component arrays of N values:
+//   per-pass parameters: one splitmix64 draw per component k gives an odd
+//   stride a_k and an offset b_k (eq. 2, sections 3 and 8) and, for n = 16,
+//   a column sign;
+//   gather v_k[j] = X_k[(a_k j + b_k) mod N];
+//   y[j] = h * (butterflies of v[j]) with h = RN32(c) times the matrix's
+//   power-of-two factor; c is the chi-squared scale computed from the old
+//   pool (section 4, eq. 3), folded into the matrix as section 4 notes;
+//   the new pool replaces the old (double buffering, section 2), is returned
+//   in flat order f = k*N + j (section 3), and its sum of squares is formed
+//   for the next pass (section 4).
+//
+// A group of L lanes owns one pool for a whole job and keeps it in registers:
+// lane l holds tuples T*l .. T*l+T-1 of every component. LDS is the per-pass
+// permutation network, C = n/NST components at a time, each component stored
+// in natural order (a lane writes its T values with one vector store; a
+// gather is one 24-bit multiply-add and one and-or for the address). The
+// per-pass draws are counter-based (splitmix64 draw m is a function of
+// state + m * gamma), so each lane computes one pass's parameters for a chunk
+// of up to 64 passes at once and every pass reads its parameters with one
+// lane read per component. T and L are compile-time, so every LDS and store
+// offset is an immediate.
+//
+// Bit-exactness: no FMA contraction (-ffp-contract=off), butterflies in a
+// fixed order, and the sum of squares as the canonical pairwise tree over
+// the flat index. FP64 leaves y*y are exact, so fma(y1, y1, y0*y0) equals
+// the tree node y0^2 + y1^2 rounded once.
+#pragma once
+
+#include <type_traits>
+
+#include "wallace_internal.h"
+#include "wallace.h"
+
+namespace wallace {
+namespace pool {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+template <int V>
+struct Log2 {
+    static constexpr int value = 1 + Log2<V / 2>::value;
+};
+template <>
+struct Log2<1> {
+    static constexpr int value = 0;
+};
+
+// splitmix64 (Steele, Lea and Flood 2014): Weyl step, two xor-shift-multiply
+// rounds and a final xor-shift.
+__device__ __forceinline__ uint64_t sm64_next(uint64_t &s)
+{
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// The splitmix64 output for state value z (after the Weyl step).
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+// Stride pair of component k: RANN4's {3,5} and {7,11} (section 8), then
+// further odd primes, so strides of different components differ and exceed
+// one (sections 3 and 7).
+__device__ __forceinline__ uint32_t stride_pick(int k, uint32_t top)
+{
+    constexpr uint32_t lo[16] = {3, 7, 13, 19, 29, 37, 43, 53,
+                                 61, 71, 79, 89, 101, 107, 113, 131};
+    constexpr uint32_t hi[16] = {5, 11, 17, 23, 31, 41, 47, 59,
+                                 67, 73, 83, 97, 103, 109, 127, 137};
+    return top ? hi[k] : lo[k];
+}
+
+// Chi-squared scale (section 4, eq. 3): S = (x* + sqrt(2 nu - 1))^2 / 2,
+// c = sqrt(S / sigma), each step one correctly rounded FP64 operation.
+__device__ __forceinline__ float chi2_scale(double xstar, double sigma, double r_nu)
+{
+    const double t = xstar + r_nu;
+    const double S = (t * t) * 0.5;
+    const double q = S / sigma;
+    return (float)__builtin_sqrt(q);
+}
+
+template <bool MW>
+__device__ __forceinline__ void group_sync()
+{
+    if constexpr (MW) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    } else {
+        // one wave: LDS executes its instructions in order; only the
+        // compiler must not move LDS accesses across this point
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
+// Exchange of a 32-bit value with lane (lane ^ M), M = 1..32. Every partner
+// is the exact xor partner, so the same helper serves reductions whose lanes
+// hold different values.
+template <int M>
+__device__ __forceinline__ int xchg(int v)
+{
+    if constexpr (M == 1)
+        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+    else if constexpr (M == 2)
+        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    else if constexpr (M == 4 || M == 8 || M == 16)
+        return __builtin_amdgcn_ds_swizzle(v, 0x1F | (M << 10));  // bit mode, xor M
+    else
+        return __builtin_amdgcn_ds_bpermute((int)((__lane_id() ^ 32u) << 2), v);
+}
+
+template <int M>
+__device__ __forceinline__ float xchg(float v)
+{
+    return __int_as_float(xchg<M>(__float_as_int(v)));
+}
+
+template <int M>
+__device__ __forceinline__ double xchg(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(xchg<M>(hi), xchg<M>(lo));
+}
+
+// Sum-of-squares tree nodes of the three reduction modes.
+struct NodeF64 {  // FP64 nodes; leaves (double)y * (double)y are exact
+    double v;
+    __device__ static NodeF64 leaf(float y) { return {(double)y * (double)y}; }
+    // node of the pair (y0, y1): one rounding of y0^2 + y1^2
+    __device__ static NodeF64 leaf2(float y0, float y1)
+    {
+        const double d0 = (double)y0, d1 = (double)y1;
+        return {__builtin_fma(d1, d1, d0 * d0)};
+    }
+    __device__ static NodeF64 zero() { return {0.0}; }
+    __device__ static NodeF64 join(NodeF64 a, NodeF64 b) { return {a.v + b.v}; }
+    template <int M>
+    __device__ static NodeF64 xch(NodeF64 a) { return {xchg<M>(a.v)}; }
+    __device__ static NodeF64 sel(bool c, NodeF64 a, NodeF64 b) { return c ? a : b; }
+    __device__ double value() const { return v; }
+    __device__ void put(char *p) const { *reinterpret_cast<double *>(p) = v; }
+    __device__ static NodeF64 get(const char *p) { return {*reinterpret_cast<const double *>(p)}; }
+    __device__ NodeF64 uniform() const
+    {
+        return {__hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                                 __builtin_amdgcn_readfirstlane(__double2loint(v)))};
+    }
+    static constexpr int kBytes = 8;
+};
+
+struct NodeF32 {  // FP32 nodes (the plain FP32 reduction)
+    float v;
+    __device__ static NodeF32 leaf(float y) { return {y * y}; }
+    __device__ static NodeF32 leaf2(float y0, float y1) { return join(leaf(y0), leaf(y1)); }
+    __device__ static NodeF32 zero() { return {0.0f}; }
+    __device__ static NodeF32 join(NodeF32 a, NodeF32 b) { return {a.v + b.v}; }
+    template <int M>
+    __device__ static NodeF32 xch(NodeF32 a) { return {xchg<M>(a.v)}; }
+    __device__ static NodeF32 sel(bool c, NodeF32 a, NodeF32 b) { return c ? a : b; }
+    __device__ double value() const { return (double)v; }
+    __device__ void put(char *p) const { *reinterpret_cast<float *>(p) = v; }
+    __device__ static NodeF32 get(const char *p) { return {*reinterpret_cast<const float *>(p)}; }
+    __device__ NodeF32 uniform() const
+    {
+        return {__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)))};
+    }
+    static constexpr int kBytes = 4;
+};
+
+struct NodeComp {  // FP32 value and FP32 error term (TwoProd leaves, TwoSum joins)
+    float s, e;
+    __device__ static NodeComp leaf(float y)
+    {
+        const float p = y * y;
+        return {p, __builtin_fmaf(y, y, -p)};
+    }
+    __device__ static NodeComp leaf2(float y0, float y1) { return join(leaf(y0), leaf(y1)); }
+    __device__ static NodeComp zero() { return {0.0f, 0.0f}; }
+    __device__ static NodeComp join(NodeComp a, NodeComp b)
+    {
+        const float sum = a.s + b.s;
+        const float bb = sum - a.s;
+        const float err = (a.s - (sum - bb)) + (b.s - bb);
+        return {sum, (a.e + b.e) + err};
+    }
+    template <int M>
+    __device__ static NodeComp xch(NodeComp a) { return {xchg<M>(a.s), xchg<M>(a.e)}; }
+    __device__ static NodeComp sel(bool c, NodeComp a, NodeComp b) { return c ? a : b; }
+    __device__ double value() const { return (double)s + (double)e; }
+    __device__ void put(char *p) const { *reinterpret_cast<v2f *>(p) = v2f{s, e}; }
+    __device__ static NodeComp get(const char *p)
+    {
+        const v2f q = *reinterpret_cast<const v2f *>(p);
+        return {q.x, q.y};
+    }
+    __device__ NodeComp uniform() const
+    {
+        return {__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s))),
+                __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(e)))};
+    }
+    static constexpr int kBytes = 8;
+};
+
+template <int RM>
+struct NodeOf {
+    using type = NodeF64;
+};
+template <>
+struct NodeOf<1> {
+    using type = NodeF32;
+};
+template <>
+struct NodeOf<2> {
+    using type = NodeComp;
+};
+
+// Canonical tree over the T consecutive values of one component in a lane.
+template <class Nd, int T>
+__device__ __forceinline__ Nd lane_tree(const float (&x)[T])
+{
+    if constexpr (T == 1) {
+        return Nd::leaf(x[0]);
+    } else {
+        Nd t[T / 2];
+#pragma unroll
+        for (int i = 0; i < T / 2; ++i) t[i] = Nd::leaf2(x[2 * i], x[2 * i + 1]);
+#pragma unroll
+        for (int w = T / 2; w > 1; w >>= 1) {
+#pragma unroll
+            for (int i = 0; i < w / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
+        }
+        return t[0];
+    }
+}
+
+// Butterfly over lane bits [M0, log2 W): afterwards every lane of each
+// aligned group of W lanes holds the group's node.
+template <class Nd, int M, int W>
+__device__ __forceinline__ Nd butterfly(Nd a)
+{
+    if constexpr (M >= W) {
+        return a;
+    } else {
+        a = Nd::join(a, Nd::template xch<M>(a));
+        return butterfly<Nd, 2 * M, W>(a);
+    }
+}
+
+// One halving level at lane bit m (mask M = 2^m): a lane keeps half of the
+// V components it carries and adds the partner's node of the same
+// components (the partner keeps the other half).
+template <class Nd, int M, int V>
+__device__ __forceinline__ void halve(Nd (&v)[16], bool hi)
+{
+#pragma unroll
+    for (int t = 0; t < V / 2; ++t) {
+        const Nd keep = Nd::sel(hi, v[t + V / 2], v[t]);
+        const Nd send = Nd::sel(hi, v[t], v[t + V / 2]);
+        v[t] = Nd::join(keep, Nd::template xch<M>(send));
+    }
+}
+
+template <class Nd, int M, int V>
+__device__ __forceinline__ void halve_all(Nd (&v)[16], int wl)
+{
+    if constexpr (V > 1) {
+        halve<Nd, M, V>(v, (wl & M) != 0);
+        halve_all<Nd, 2 * M, V / 2>(v, wl);
+    }
+}
+
+// Component levels after halving: kappa and kappa ^ 2^q sit in lanes that
+// differ in bit log2(n) - 1 - q.
+template <class Nd, int M>
+__device__ __forceinline__ Nd comp_levels(Nd a)
+{
+    if constexpr (M == 0) {
+        return a;
+    } else {
+        a = Nd::join(a, Nd::template xch<M>(a));
+        return comp_levels<Nd, M / 2>(a);
+    }
+}
+
+template <int NC, int T, int L, int RM, int NST>
+struct Cfg {
+    static constexpr int N = T * L;
+    static constexpr int C = NC / NST;
+    static constexpr bool MW = L > 64;
+    static constexpr bool UNIFORM = L >= 64;   // a group is one or more whole waves
+    static constexpr int GPB = MW ? 1 : 256 / L;   // groups per block
+    static constexpr int BLOCK = MW ? L : 256;
+    static constexpr int W = MW ? L / 64 : 1;      // waves per group
+    using Nd = typename NodeOf<RM>::type;
+    // single-wave groups reuse their permutation-network space for the
+    // reduction transpose (n*L nodes)
+    static constexpr int POOL_BYTES = C * N * 4;
+    static constexpr int RED_BYTES = MW ? 0 : NC * L * Nd::kBytes;
+    static constexpr int GROUP_RAW = POOL_BYTES > RED_BYTES ? POOL_BYTES : RED_BYTES;
+    // multiple of 4N bytes, so a component's offset can be or-ed into an
+    // address masked to 4N - 4
+    static constexpr int GROUP_BYTES = (GROUP_RAW + 4 * N - 1) / (4 * N) * (4 * N);
+    static constexpr int CH = L >= 64 ? 64 : L;  // passes per parameter chunk
+    static constexpr int XW_BYTES = MW ? 16 * W * NC : 0;  // cross-wave nodes
+    static constexpr int LDS_BYTES = GPB * GROUP_BYTES + XW_BYTES;
+};
+
+// Sum of squares of a pool held by a group (see the file comment).
+template <int NC, int T, int L, int RM, int NST>
+__device__ __forceinline__ double pool_sumsq(const float (&X)[NC][T], int lane, char *grp_lds,
+                                             char *xw_lds)
+{
+    using C = Cfg<NC, T, L, RM, NST>;
+    using Nd = typename C::Nd;
+    constexpr int LOG_NC = Log2<NC>::value;
+    Nd v[16];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) v[k] = lane_tree<Nd, T>(X[k]);
+    if constexpr (!C::MW) {
+        // transpose through LDS: node (k, lane) -> flat slot k*L + lane; then
+        // lane m owns slots NC*m .. NC*m+NC-1, joins them in tree order and
+        // the lanes finish with a butterfly
+        group_sync<false>();
+#pragma unroll
+        for (int k = 0; k < NC; ++k) v[k].put(grp_lds + (k * L + lane) * Nd::kBytes);
+        group_sync<false>();
+        Nd t[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) t[q] = Nd::get(grp_lds + (NC * lane + q) * Nd::kBytes);
+#pragma unroll
+        for (int w = NC; w > 1; w >>= 1) {
+#pragma unroll
+            for (int i = 0; i < w / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
+        }
+        const Nd r = butterfly<Nd, 1, L>(t[0]);
+        return (C::UNIFORM ? r.uniform() : r).value();
+    } else {
+        const int wl = lane & 63;
+        const int wave = lane >> 6;
+        halve_all<Nd, 1, NC>(v, wl);
+        Nd acc = butterfly<Nd, NC, 64>(v[0]);
+        int kappa = 0;
+#pragma unroll
+        for (int m = 0; m < LOG_NC; ++m) kappa |= ((wl >> m) & 1) << (LOG_NC - 1 - m);
+        group_sync<true>();  // earlier readers of the cross-wave area are done
+        if (wl < NC) acc.put(xw_lds + (wave * NC + kappa) * 16);
+        group_sync<true>();
+        Nd t[C::W];
+#pragma unroll
+        for (int w = 0; w < C::W; ++w) t[w] = Nd::get(xw_lds + (w * NC + kappa) * 16);
+#pragma unroll
+        for (int s = C::W; s > 1; s >>= 1) {
+#pragma unroll
+            for (int i = 0; i < s / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
+        }
+        acc = comp_levels<Nd, NC / 2>(t[0]);
+        // lanes 0..NC-1 of every wave now hold the total; lane 0 is uniform
+        return acc.uniform().value();
+    }
+}
+
+// n = 4: A0 = H4/2 (mat 0) and A1 = J/2 - I (mat 1) with
+// A1 = D_r P (H4/2) D_c, D_c = diag(-1,1,1,1), P swapping rows 1 and 2,
+// D_r = diag(1,-1,-1,-1).
+__device__ __forceinline__ void xform4(float (&v)[4], int mat, float h)
+{
+    const float v0 = mat ? -v[0] : v[0];
+    const float s0 = v0 + v[1], s1 = v0 - v[1];
+    const float s2 = v[2] + v[3], s3 = v[2] - v[3];
+    const float u0 = s0 + s2, u1 = s1 + s3, u2 = s0 - s2, u3 = s1 - s3;
+    if (mat) {
+        v[0] = u0 * h;
+        v[1] = (-u2) * h;
+        v[2] = (-u1) * h;
+        v[3] = (-u3) * h;
+    } else {
+        v[0] = u0 * h;
+        v[1] = u1 * h;
+        v[2] = u2 * h;
+        v[3] = u3 * h;
+    }
+}
+
+// n = 16: H16 D / 4, D = diag((-1)^(bit k of signs)), radix-2 stages 1,2,4,8.
+__device__ __forceinline__ void xform16(float (&v)[16], uint32_t signs, float h)
+{
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = ((signs >> k) & 1u) ? -v[k] : v[k];
+#pragma unroll
+    for (int s = 1; s < 16; s <<= 1) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i & s) continue;
+            const float lo = v[i], hi = v[i + s];
+            v[i] = lo + hi;
+            v[i + s] = lo - hi;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = v[k] * h;
+}
+
+template <int T>
+__device__ __forceinline__ void load_run(float (&x)[T], const float *p)
+{
+    if constexpr (T % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < T; i += 4) {
+            const v4f q = *reinterpret_cast<const v4f *>(p + i);
+            x[i] = q.x;
+            x[i + 1] = q.y;
+            x[i + 2] = q.z;
+            x[i + 3] = q.w;
+        }
+    } else if constexpr (T == 2) {
+        const v2f q = *reinterpret_cast<const v2f *>(p);
+        x[0] = q.x;
+        x[1] = q.y;
+    } else {
+        x[0] = p[0];
+    }
+}
+
+template <int T>
+__device__ __forceinline__ void store_run(float *p, const float (&x)[T], bool nt)
+{
+    if constexpr (T % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < T; i += 4) {
+            const v4f q = {x[i], x[i + 1], x[i + 2], x[i + 3]};
+            if (nt)
+                __builtin_nontemporal_store(q, reinterpret_cast<v4f *>(p + i));
+            else
+                *reinterpret_cast<v4f *>(p + i) = q;
+        }
+    } else if constexpr (T == 2) {
+        const v2f q = {x[0], x[1]};
+        if (nt)
+            __builtin_nontemporal_store(q, reinterpret_cast<v2f *>(p));
+        else
+            *reinterpret_cast<v2f *>(p) = q;
+    } else {
+        if (nt)
+            __builtin_nontemporal_store(x[0], p);
+        else
+            p[0] = x[0];
+    }
+}
+
+// A lane's T consecutive values into LDS with vector stores.
+template <int T>
+__device__ __forceinline__ void store_lds(float *p, const float (&x)[T])
+{
+    if constexpr (T % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < T; i += 4)
+            *reinterpret_cast<v4f *>(p + i) = v4f{x[i], x[i + 1], x[i + 2], x[i + 3]};
+    } else if constexpr (T == 2) {
+        *reinterpret_cast<v2f *>(p) = v2f{x[0], x[1]};
+    } else {
+        p[0] = x[0];
+    }
+}
+
+// Element-wise emission: partial pools, unaligned outputs, N(mu, sigma^2).
+template <int NC, int T, int N>
+__device__ __forceinline__ void emit_slow(const float (&X)[NC][T], float *base, uint32_t cnt,
+                                          int lane, uint32_t affine, float mu, float sig)
+{
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            const uint32_t fl = (uint32_t)(k * N) + (uint32_t)(T * lane + i);
+            if (fl < cnt) {
+                float y = X[k][i];
+                if (affine) y = mu + sig * y;
+                __builtin_nontemporal_store(y, base + fl);
+            }
+        }
+    }
+}
+
+// Lane-broadcast of a per-lane word within the group: lane `src` (< CH) of
+// the wave (groups of >= 64 lanes) or of the group (smaller groups).
+template <int L>
+__device__ __forceinline__ uint32_t bcast(uint32_t v, uint32_t src)
+{
+    if constexpr (L >= 64)
+        return __builtin_amdgcn_readlane(v, src);
+    else
+        return (uint32_t)__shfl((int)v, (int)src, L);
+}
+
+// Draws of pass `pass` (0-based within the job) for component k, from the
+// job's starting splitmix64 state: draw number NC*pass + k + 1.
+template <int NC, int N>
+__device__ __forceinline__ uint32_t pass_word(uint64_t rng0, uint32_t pass, int k,
+                                              uint32_t a_mode, uint32_t *signs)
+{
+    constexpr uint32_t mask = (uint32_t)N - 1u;
+    const uint64_t m = (uint64_t)NC * pass + (uint64_t)(k + 1);
+    const uint64_t w = sm64_mix(rng0 + m * kGamma);
+    const uint32_t ak = a_mode ? ((uint32_t)(w >> 32) | 1u) : stride_pick(k, (uint32_t)(w >> 63));
+    const uint32_t a = ak & mask, b = (uint32_t)w & mask;
+    if (NC == 16) *signs |= (uint32_t)((w >> 62) & 1u) << k;
+    return (a << 2) | ((b << 2) << 16);  // 4a | 4b << 16 (N <= 2^14)
+}
+
+template <int NC, int T, int L, int RM, int NST>
+__device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw, int lane)
+{
+    using Cf = Cfg<NC, T, L, RM, NST>;
+    constexpr int N = Cf::N;
+    constexpr int C = Cf::C;
+    constexpr int CH = Cf::CH;
+    constexpr bool MW = Cf::MW;
+    constexpr uint32_t nu = (uint32_t)(NC * N);
+    constexpr uint32_t amask = 4u * (uint32_t)N - 4u;
+    static_assert(N <= (1 << 14), "packed parameters need N <= 2^14");
+    char *grp_bytes = reinterpret_cast<char *>(lds);
+
+    float X[NC][T];
+    const float *pool = P.pools + job.pool_off;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) load_run<T>(X[k], pool + k * N + T * lane);
+
+    GenState *stp = P.states + job.gen;
+    const uint64_t rng0 = stp->rng;
+    double sigma = stp->sigma;
+    const uint64_t done = stp->passes;
+    uint32_t flags = stp->flags;
+
+    if (P.sigma_mode) {
+        const double s = pool_sumsq<NC, T, L, RM, NST>(X, lane, grp_bytes, xw);
+        if (P.sigma_mode == 2)
+            sigma = s;
+        else if (!(s == sigma))
+            flags |= WALLACE_FLAG_CORRUPT;
+    }
+    const uint32_t passes = (flags & WALLACE_FLAG_CORRUPT) ? 0u : job.passes;
+    const uint32_t qlane = (uint32_t)lane % (uint32_t)CH;  // pass slot this lane computes
+    const uint32_t j0 = (uint32_t)(T * lane);               // first tuple of this lane
+
+    uint32_t words[NC];  // packed (4a, 4b) of pass chunk + qlane, per component
+    uint32_t swords = 0; // column signs of that pass (n = 16)
+    uint32_t slot = 0;   // pass index within the chunk
+    uint32_t fcount = 0; // passes since the last returned pool
+    uint32_t emitted = 0;
+
+    // One pass with the matrix fixed at compile time (n = 4 alternates A0
+    // and A1; a uniform branch picks the body, so no per-value selects).
+    auto one_pass = [&](uint32_t ps, auto mat_c) {
+        constexpr int MAT = decltype(mat_c)::value;
+        if (slot == 0) {
+            // this lane's pass of the next chunk (eq. 1, section 8 draws)
+            swords = 0;
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+                words[k] = pass_word<NC, N>(rng0, ps + qlane, k, P.a_mode, &swords);
+        }
+        const uint32_t signs = NC == 16 ? bcast<L>(swords, slot) : 0u;
+        double xstar = 0.0;
+#pragma unroll
+        for (int st = 0; st < NST; ++st) {
+            group_sync<MW>();  // previous readers of this LDS space are done
+#pragma unroll
+            for (int c = 0; c < C; ++c) store_lds<T>(lds + c * N + T * lane, X[st * C + c]);
+            group_sync<MW>();
+            if (st == NST - 1)  // the old pool's last flat value (section 4)
+                xstar = (double)lds[(C - 1) * N + (N - 1)];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const uint32_t wd = bcast<L>(words[st * C + c], slot);
+                const uint32_t a4 = wd & 0xFFFFu, b4 = wd >> 16;
+                const char *src = reinterpret_cast<const char *>(lds + c * N);
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    // 4 * ((a j + b) mod N) for tuple j = T*lane + i
+                    const uint32_t x4 = (__umul24(a4, j0 + i) + b4) & amask;
+                    X[st * C + c][i] = *reinterpret_cast<const float *>(src + x4);
+                }
+            }
+        }
+        slot = (slot + 1 == (uint32_t)CH) ? 0u : slot + 1;
+
+        const float c32 = chi2_scale(xstar, sigma, P.r_nu);
+        if (!__builtin_isfinite(c32)) flags |= WALLACE_FLAG_NONFINITE;
+        const float h = c32 * (NC == 4 ? 0.5f : 0.25f);
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            float v[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) v[k] = X[k][i];
+            if constexpr (NC == 4)
+                xform4(v, MAT, h);
+            else
+                xform16(v, signs, h);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) X[k][i] = v[k];
+        }
+
+        // return the new pool when it is a returned one (section 6)
+        if (++fcount == P.f) {
+            fcount = 0;
+            const bool last = (ps + 1 == passes);
+            const uint32_t cnt = last ? job.last_emit : P.emit_len;
+            float *base = P.out + job.out_off + (uint64_t)emitted * P.emit_len;
+            ++emitted;
+            constexpr uintptr_t vmask = (uintptr_t)(4 * (T >= 4 ? 4 : T) - 1);
+            if (cnt == nu && ((uintptr_t)base & vmask) == 0 && !P.affine) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) store_run<T>(base + k * N + T * lane, X[k], true);
+            } else {
+                emit_slow<NC, T, N>(X, base, cnt, lane, P.affine, P.mu, P.sigma_out);
+            }
+        }
+
+        sigma = pool_sumsq<NC, T, L, RM, NST>(X, lane, grp_bytes, xw);
+    };
+
+    for (uint32_t ps = 0; ps < passes; ++ps) {
+        if (NC == 4 && ((done + ps) & 1u))
+            one_pass(ps, std::integral_constant<int, 1>());
+        else
+            one_pass(ps, std::integral_constant<int, 0>());
+    }
+
+    float *wpool = P.pools + job.pool_off;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) store_run<T>(wpool + k * N + T * lane, X[k], false);
+    if (lane == 0) {
+        stp->rng = rng0 + (uint64_t)NC * passes * kGamma;
+        stp->sigma = sigma;
+        stp->passes = done + passes;
+        stp->flags = flags;
+    }
+}
+
+template <int NC, int T, int L, int RM, int NST>
+__global__ __launch_bounds__((L > 64 ? L : 256)) void k_pool(PoolArgs P)
+{
+    using Cf = Cfg<NC, T, L, RM, NST>;
+    extern __shared__ __attribute__((aligned(16))) char lds_all[];
+    const int grp = (int)threadIdx.x / L;
+    const int lane = (int)threadIdx.x % L;
+    float *lds = reinterpret_cast<float *>(lds_all + grp * Cf::GROUP_BYTES);
+    char *xw = lds_all + Cf::GPB * Cf::GROUP_BYTES;
+    const uint32_t total = gridDim.x * (uint32_t)Cf::GPB;
+    uint32_t j = blockIdx.x * (uint32_t)Cf::GPB + (uint32_t)grp;
+    if constexpr (Cf::UNIFORM) j = __builtin_amdgcn_readfirstlane(j);
+    for (; j < P.njobs; j += total) {
+        const Job job = P.jobs ? P.jobs[j] : P.one;
+        run_job<NC, T, L, RM, NST>(P, job, lds, xw, lane);
+    }
+}
+
+// Shapes instantiated for each (n, reduction mode): single-wave groups
+// (L <= 64) keep all components on chip; multi-wave groups use one stage,
+// or two when the n*N floats exceed 128 KiB.
+#define WALLACE_POOL_SHAPES_4(X)                                                         \
+    X(4, 1, 4, 1) X(4, 1, 8, 1) X(4, 1, 16, 1) X(4, 1, 32, 1) X(4, 1, 64, 1)             \
+    X(4, 2, 4, 1) X(4, 2, 8, 1) X(4, 2, 16, 1) X(4, 2, 32, 1) X(4, 2, 64, 1)             \
+    X(4, 4, 4, 1) X(4, 4, 8, 1) X(4, 4, 16, 1) X(4, 4, 32, 1) X(4, 4, 64, 1)             \
+    X(4, 8, 4, 1) X(4, 8, 8, 1) X(4, 8, 16, 1) X(4, 8, 32, 1) X(4, 8, 64, 1)             \
+    X(4, 16, 4, 1) X(4, 16, 8, 1) X(4, 16, 16, 1) X(4, 16, 32, 1) X(4, 16, 64, 1)        \
+    X(4, 1, 128, 1) X(4, 1, 256, 1) X(4, 1, 512, 1) X(4, 1, 1024, 1)                     \
+    X(4, 2, 128, 1) X(4, 2, 256, 1) X(4, 2, 512, 1) X(4, 2, 1024, 1)                     \
+    X(4, 4, 128, 1) X(4, 4, 256, 1) X(4, 4, 512, 1) X(4, 4, 1024, 1)                     \
+    X(4, 8, 128, 1) X(4, 8, 256, 1) X(4, 8, 512, 1) X(4, 8, 1024, 1)                     \
+    X(4, 16, 128, 1) X(4, 16, 256, 1) X(4, 16, 512, 1) X(4, 16, 1024, 2)
+
+#define WALLACE_POOL_SHAPES_16(X)                                                        \
+    X(16, 1, 16, 1) X(16, 1, 32, 1) X(16, 1, 64, 1)                                      \
+    X(16, 2, 16, 1) X(16, 2, 32, 1) X(16, 2, 64, 1)                                      \
+    X(16, 4, 16, 1) X(16, 4, 32, 1) X(16, 4, 64, 1)                                      \
+    X(16, 1, 128, 1) X(16, 1, 256, 1) X(16, 1, 512, 1) X(16, 1, 1024, 1)                 \
+    X(16, 2, 128, 1) X(16, 2, 256, 1) X(16, 2, 512, 1) X(16, 2, 1024, 1)                 \
+    X(16, 4, 128, 1) X(16, 4, 256, 1) X(16, 4, 512, 1) X(16, 4, 1024, 2)
+
+// Entry of the kernel table: shape and kernel address.
+struct PoolEntry {
+    int n, T, L, nst;
+    const void *fn;
+    int lds_bytes, block;
+};
+
+}  // namespace pool
+}  // namespace wallace

@@ -78,9 +78,13 @@ hipError_t class_grid(ClassInfo &c, int cus, uint32_t rmode)
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     const int gpb = c.sched.L > 64 ? 1 : 256 / c.sched.L;
+    // One block per gpb jobs: the dispatcher then hands out jobs in plan
+    // order as blocks retire, which streams the output faster than a
+    // resident grid looping over jobs. Very large classes loop (the kernel
+    // strides by the grid).
     const uint64_t need = (c.job_count + (uint32_t)gpb - 1) / (uint32_t)gpb;
-    const uint64_t resident = (uint64_t)per_cu * (uint64_t)cus;
-    c.grid = (int)std::max<uint64_t>(1, std::min(need, resident));
+    const uint64_t cap = std::max<uint64_t>((uint64_t)per_cu * (uint64_t)cus, 1u << 20);
+    c.grid = (int)std::max<uint64_t>(1, std::min(need, cap));
     return hipSuccess;
 }
 

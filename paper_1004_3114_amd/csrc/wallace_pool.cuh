@@ -16,8 +16,10 @@
 // A group of L lanes owns one pool for a whole job and keeps it in registers:
 // lane l holds tuples T*l .. T*l+T-1 of every component. LDS is the per-pass
 // permutation network, C = n/NST components at a time, each component stored
-// in natural order (a lane writes its T values with one vector store; a
-// gather is one 24-bit multiply-add and one and-or for the address). The
+// in natural order (a lane writes its T values with one vector store). Small
+// components are stored twice back to back: a lane's T gathers then share
+// one base address (a j0 + b) mod N and add the wave-uniform a i mod N, with
+// no wrap-around per value. The
 // per-pass draws are counter-based (splitmix64 draw m is a function of
 // state + m * gamma), so each lane computes one pass's parameters for a chunk
 // of up to 64 passes at once and every pass reads its parameters with one
@@ -114,9 +116,9 @@ template <int M>
 __device__ __forceinline__ int xchg(int v)
 {
     if constexpr (M == 1)
-        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+        return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);  // quad_perm 1,0,3,2
     else if constexpr (M == 2)
-        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+        return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm 2,3,0,1
     else if constexpr (M == 4 || M == 8 || M == 16)
         return __builtin_amdgcn_ds_swizzle(v, 0x1F | (M << 10));  // bit mode, xor M
     else
@@ -306,9 +308,13 @@ struct Cfg {
     static constexpr int BLOCK = MW ? L : 256;
     static constexpr int W = MW ? L / 64 : 1;      // waves per group
     using Nd = typename NodeOf<RM>::type;
+    // Small components are stored twice in a row in LDS, so the gather
+    // address x0 + d with x0, d < N needs no wrap-around.
+    static constexpr bool DUP = C * N <= 2048;
+    static constexpr int CSTRIDE = DUP ? 2 * N : N;  // floats between components
     // single-wave groups reuse their permutation-network space for the
     // reduction transpose (n*L nodes)
-    static constexpr int POOL_BYTES = C * N * 4;
+    static constexpr int POOL_BYTES = C * CSTRIDE * 4;
     static constexpr int RED_BYTES = MW ? 0 : NC * L * Nd::kBytes;
     static constexpr int GROUP_RAW = POOL_BYTES > RED_BYTES ? POOL_BYTES : RED_BYTES;
     // multiple of 4N bytes, so a component's offset can be or-ed into an
@@ -528,6 +534,7 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
     constexpr int N = Cf::N;
     constexpr int C = Cf::C;
     constexpr int CH = Cf::CH;
+    constexpr int CS = Cf::CSTRIDE;
     constexpr bool MW = Cf::MW;
     constexpr uint32_t nu = (uint32_t)(NC * N);
     constexpr uint32_t amask = 4u * (uint32_t)N - 4u;
@@ -559,6 +566,14 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
     uint32_t words[NC];  // packed (4a, 4b) of pass chunk + qlane, per component
     uint32_t swords = 0; // column signs of that pass (n = 16)
     uint32_t slot = 0;   // pass index within the chunk
+    auto draw_chunk = [&](uint32_t ps0) {
+        // this lane's pass of the chunk starting at ps0 (eq. 1, section 8 draws)
+        swords = 0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            words[k] = pass_word<NC, N>(rng0, ps0 + qlane, k, P.a_mode, &swords);
+        slot = 0;
+    };
     uint32_t fcount = 0; // passes since the last returned pool
     uint32_t emitted = 0;
 
@@ -566,37 +581,44 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
     // and A1; a uniform branch picks the body, so no per-value selects).
     auto one_pass = [&](uint32_t ps, auto mat_c) {
         constexpr int MAT = decltype(mat_c)::value;
-        if (slot == 0) {
-            // this lane's pass of the next chunk (eq. 1, section 8 draws)
-            swords = 0;
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-                words[k] = pass_word<NC, N>(rng0, ps + qlane, k, P.a_mode, &swords);
-        }
         const uint32_t signs = NC == 16 ? bcast<L>(swords, slot) : 0u;
         double xstar = 0.0;
 #pragma unroll
         for (int st = 0; st < NST; ++st) {
             group_sync<MW>();  // previous readers of this LDS space are done
 #pragma unroll
-            for (int c = 0; c < C; ++c) store_lds<T>(lds + c * N + T * lane, X[st * C + c]);
+            for (int c = 0; c < C; ++c) {
+                store_lds<T>(lds + c * CS + T * lane, X[st * C + c]);
+                if constexpr (Cf::DUP) store_lds<T>(lds + c * CS + N + T * lane, X[st * C + c]);
+            }
             group_sync<MW>();
             if (st == NST - 1)  // the old pool's last flat value (section 4)
-                xstar = (double)lds[(C - 1) * N + (N - 1)];
+                xstar = (double)lds[(C - 1) * CS + (N - 1)];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const uint32_t wd = bcast<L>(words[st * C + c], slot);
                 const uint32_t a4 = wd & 0xFFFFu, b4 = wd >> 16;
-                const char *src = reinterpret_cast<const char *>(lds + c * N);
+                const char *src = reinterpret_cast<const char *>(lds + c * CS);
+                if constexpr (Cf::DUP) {
+                    // 4 * ((a j + b) mod N) = x0 + 4 * (a i mod N) - (0 or 4N),
+                    // and the second image absorbs the 4N
+                    const uint32_t x0 = (__umul24(a4, j0) + b4) & amask;
 #pragma unroll
-                for (int i = 0; i < T; ++i) {
-                    // 4 * ((a j + b) mod N) for tuple j = T*lane + i
-                    const uint32_t x4 = (__umul24(a4, j0 + i) + b4) & amask;
-                    X[st * C + c][i] = *reinterpret_cast<const float *>(src + x4);
+                    for (int i = 0; i < T; ++i) {
+                        const uint32_t d4 = (a4 * (uint32_t)i) & amask;  // wave-uniform
+                        X[st * C + c][i] = *reinterpret_cast<const float *>(src + x0 + d4);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < T; ++i) {
+                        // 4 * ((a j + b) mod N) for tuple j = T*lane + i
+                        const uint32_t x4 = (__umul24(a4, j0 + i) + b4) & amask;
+                        X[st * C + c][i] = *reinterpret_cast<const float *>(src + x4);
+                    }
                 }
             }
         }
-        slot = (slot + 1 == (uint32_t)CH) ? 0u : slot + 1;
+        ++slot;
 
         const float c32 = chi2_scale(xstar, sigma, P.r_nu);
         if (!__builtin_isfinite(c32)) flags |= WALLACE_FLAG_NONFINITE;
@@ -633,11 +655,22 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
         sigma = pool_sumsq<NC, T, L, RM, NST>(X, lane, grp_bytes, xw);
     };
 
-    for (uint32_t ps = 0; ps < passes; ++ps) {
-        if (NC == 4 && ((done + ps) & 1u))
-            one_pass(ps, std::integral_constant<int, 1>());
-        else
-            one_pass(ps, std::integral_constant<int, 0>());
+    // Chunks of CH passes (CH is even, so every chunk starts on the same
+    // matrix); two passes per iteration (n = 4: A0 then A1), so the sum of
+    // squares of one pass and the permutation of the next share a block.
+    using M0 = std::integral_constant<int, 0>;
+    using M1 = std::integral_constant<int, NC == 4 ? 1 : 0>;
+    const bool odd = NC == 4 && (done & 1u);
+    for (uint32_t c0 = 0; c0 < passes; c0 += (uint32_t)CH) {
+        const uint32_t end = passes - c0 < (uint32_t)CH ? passes : c0 + (uint32_t)CH;
+        draw_chunk(c0);
+        uint32_t ps = c0;
+        if (odd) one_pass(ps++, M1());
+        for (; ps + 2 <= end; ps += 2) {
+            one_pass(ps, M0());
+            one_pass(ps + 1, M1());
+        }
+        if (ps < end) one_pass(ps, M0());
     }
 
     float *wpool = P.pools + job.pool_off;

@@ -1,10 +1,14 @@
-// Streaming pass for pools too large to stay on chip (tens of MB): the old
-// pool is gathered from HBM (it mostly stays in the 256 MB last-level
-// cache), the new pool is written to a second buffer and, when it is a
-// returned pool, to the caller's output. One launch per pass (section 2,
-// eq. 1); the pass's sum of squares (section 4) is reduced by the last
-// block to arrive, which also advances the generator state for the next
-// launch.
+// Streaming pass for pools too large to stay on chip (tens of MB). With the
+// prime-pair strides (section 8) a pass is two launches:
+//   permute: G_k[j] = X_k[(a_k j + b_k) mod N] (section 2, eq. 1). A block
+//     loads a contiguous run of a*R values of X_k into LDS with coalesced
+//     reads; the j whose source lies in that run form a+1 strands of R
+//     consecutive j each, which the block writes as coalesced runs of G_k.
+//   combine: reads G_k contiguously, applies the scaled transform, writes
+//     the new pool in place of G and, when it is a returned pool, the
+//     caller's output; the pass's sum of squares (section 4) is reduced by
+//     the last block to arrive, which also advances the generator state.
+// Arbitrary odd strides (eq. 2) use a single launch that gathers from HBM.
 #include "wallace_runtime.h"
 
 namespace wallace {
@@ -94,8 +98,58 @@ struct Lg<1> {
 
 constexpr int kThreads = 256;
 
+// A thread's T consecutive values of one component (16-, 8- or 4-byte
+// accesses).
+template <int T>
+__device__ __forceinline__ void load_run(float (&x)[T], const float *p)
+{
+    if constexpr (T % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < T; i += 4) {
+            const v4f q = *reinterpret_cast<const v4f *>(p + i);
+            x[i] = q.x;
+            x[i + 1] = q.y;
+            x[i + 2] = q.z;
+            x[i + 3] = q.w;
+        }
+    } else if constexpr (T == 2) {
+        const v2f q = *reinterpret_cast<const v2f *>(p);
+        x[0] = q.x;
+        x[1] = q.y;
+    } else {
+        x[0] = p[0];
+    }
+}
+
+template <int T>
+__device__ __forceinline__ void store_run(float *p, const float (&x)[T], bool nt)
+{
+    if constexpr (T % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < T; i += 4) {
+            const v4f q = {x[i], x[i + 1], x[i + 2], x[i + 3]};
+            if (nt)
+                __builtin_nontemporal_store(q, reinterpret_cast<v4f *>(p + i));
+            else
+                *reinterpret_cast<v4f *>(p + i) = q;
+        }
+    } else if constexpr (T == 2) {
+        const v2f q = {x[0], x[1]};
+        if (nt)
+            __builtin_nontemporal_store(q, reinterpret_cast<v2f *>(p));
+        else
+            *reinterpret_cast<v2f *>(p) = q;
+    } else {
+        if (nt)
+            __builtin_nontemporal_store(x[0], p);
+        else
+            p[0] = x[0];
+    }
+}
+
 struct Pass {
     const float *X;   // old pool
+    const float *G;   // permuted components (PERM kernels), else unused
     float *Y;         // new pool
     float *out;       // returned copy of the new pool (NULL: not returned)
     uint32_t emit_cnt;
@@ -103,7 +157,6 @@ struct Pass {
     float mu, sig;
     GenState *state;
     double2 *partials;  // [n][nblocks]
-    uint32_t *counter;
     double r_nu;
     uint32_t N;
     uint32_t a_mode;
@@ -157,36 +210,79 @@ __device__ void block_partials(const float (&X)[NC][T], double2 *dst,
         Nd r = Nd::join(Nd::join(Nd::unpack(red[k]), Nd::unpack(red[NC + k])),
                         Nd::join(Nd::unpack(red[2 * NC + k]), Nd::unpack(red[3 * NC + k])));
         dst[(size_t)k * nblocks + blockIdx.x] = r.pack();
-        __threadfence();
     }
 }
 
-// Canonical tree over the n*nblocks partial nodes (nblocks <= 1024): per
-// component over its blocks, then over the components.
-template <class Nd, int NC>
-__device__ double final_tree(const double2 *partials, uint32_t nblocks, double2 *red)
+// Tree over PB consecutive partial nodes.
+template <class Nd, int PB>
+__device__ __forceinline__ Nd run_tree(const double2 *p)
 {
+    Nd t[PB];
+#pragma unroll
+    for (int i = 0; i < PB; ++i) t[i] = Nd::unpack(p[i]);
+#pragma unroll
+    for (int w = PB; w > 1; w >>= 1) {
+#pragma unroll
+        for (int i = 0; i < w / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
+    }
+    return t[0];
+}
+
+constexpr int kFinThreads = 1024;
+
+// Canonical tree over the n*nblocks partial nodes (nblocks a power of two,
+// at most 4 per thread of the finish block): per component over its blocks,
+// then over the components. Four components at a time have their loads in
+// flight together. Missing nodes are zeros, which join exactly.
+template <class Nd, int NC>
+__device__ double final_tree(const double2 *partials, uint32_t nblocks)
+{
+    constexpr int NW = kFinThreads / 64;
+    constexpr int KG = NC < 4 ? NC : 4;
+    __shared__ double2 wv[NC][NW];
     __shared__ double2 comp[NC];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    for (int k = 0; k < NC; ++k) {
-        Nd t[4];
+    const uint32_t per = nblocks > kFinThreads ? nblocks / kFinThreads : 1u;
+    const uint32_t b0 = threadIdx.x * per;
+    for (int k0 = 0; k0 < NC; k0 += KG) {
+        Nd acc[KG];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t b = threadIdx.x * 4 + i;
-            t[i] = b < nblocks ? Nd::unpack(partials[(size_t)k * nblocks + b]) : Nd::zero();
+        for (int q = 0; q < KG; ++q) acc[q] = Nd::zero();
+        if (b0 < nblocks) {
+            const double2 *p = partials + (size_t)k0 * nblocks + b0;
+            if (per == 1) {
+#pragma unroll
+                for (int q = 0; q < KG; ++q) acc[q] = run_tree<Nd, 1>(p + (size_t)q * nblocks);
+            } else if (per == 2) {
+#pragma unroll
+                for (int q = 0; q < KG; ++q) acc[q] = run_tree<Nd, 2>(p + (size_t)q * nblocks);
+            } else {
+#pragma unroll
+                for (int q = 0; q < KG; ++q) acc[q] = run_tree<Nd, 4>(p + (size_t)q * nblocks);
+            }
         }
-        Nd acc = Nd::join(Nd::join(t[0], t[1]), Nd::join(t[2], t[3]));
 #pragma unroll
-        for (int m = 0; m < 6; ++m) acc = Nd::join(acc, Nd::xr(acc, 1 << m));
-        if (lane == 0) red[wave] = acc.pack();
-        __syncthreads();
-        if (threadIdx.x == 0)
-            comp[k] = Nd::join(Nd::join(Nd::unpack(red[0]), Nd::unpack(red[1])),
-                               Nd::join(Nd::unpack(red[2]), Nd::unpack(red[3])))
-                          .pack();
-        __syncthreads();
+        for (int q = 0; q < KG; ++q) {
+#pragma unroll
+            for (int m = 0; m < 6; ++m) acc[q] = Nd::join(acc[q], Nd::xr(acc[q], 1 << m));
+            if (lane == 0) wv[k0 + q][wave] = acc[q].pack();
+        }
     }
+    __syncthreads();
+    if (threadIdx.x < NC) {
+        const int k = threadIdx.x;
+        Nd t[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t[w] = Nd::unpack(wv[k][w]);
+#pragma unroll
+        for (int w = NW; w > 1; w >>= 1) {
+#pragma unroll
+            for (int i = 0; i < w / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
+        }
+        comp[k] = t[0].pack();
+    }
+    __syncthreads();
     double out = 0.0;
     if (threadIdx.x == 0) {
         Nd t[NC];
@@ -202,11 +298,100 @@ __device__ double final_tree(const double2 *partials, uint32_t nblocks, double2 
     return out;
 }
 
-template <class Nd, int NC, int T>
+// LDS run of the permute kernel: at most kRunFloats source values.
+constexpr uint32_t kRunFloats = 8192;
+constexpr int kMaxStrands = 160;  // a + 1 for the largest prime-pair stride
+
+struct Perm {
+    const float *X;        // old pool
+    float *G;              // permuted components
+    const GenState *state;
+    uint32_t N;
+    uint32_t first[17];    // first block of component k; first[n] = grid
+    uint32_t logR[16];     // strand length R_k = 2^logR[k]
+};
+
+// Permute kernel (see the file comment). Block (k, c) covers source values
+// x in [c a R, c a R + a R) of component k; strand w holds the j with
+// a j + b - w N in that run, j = c R + s_w + t (t < R) and
+// x = c a R + r_w + a t, where s_w = ceil((w N - b) / a) and
+// r_w = a s_w + b - w N lies in [0, a).
+template <int NC>
+__global__ __launch_bounds__(kThreads) void k_stream_permute(Perm P)
+{
+    extern __shared__ __attribute__((aligned(16))) float run[];
+    __shared__ int32_t s_tab[kMaxStrands];
+    __shared__ int32_t r_tab[kMaxStrands];
+    const GenState st = *P.state;
+    if (st.flags & WALLACE_FLAG_CORRUPT) return;
+    const uint32_t N = P.N;
+    int k = 0;
+#pragma unroll
+    for (int q = 1; q < NC; ++q) k += blockIdx.x >= P.first[q] ? 1 : 0;
+    const uint32_t c = blockIdx.x - P.first[k];
+    // draw k + 1 of the pass (the same draw the combine kernel makes)
+    uint64_t rng = st.rng + (uint64_t)k * 0x9E3779B97F4A7C15ull;
+    const uint64_t w64 = sm64(rng);
+    const uint32_t a = stride_of(k, (uint32_t)(w64 >> 63)) & (N - 1u);
+    const uint32_t b = (uint32_t)w64 & (N - 1u);
+    const uint32_t logR = P.logR[k];
+    const uint32_t R = 1u << logR;
+    const uint64_t X0 = (uint64_t)c * a * R;
+    if (X0 >= N) return;  // the larger stride of the pair needs fewer blocks
+    const uint32_t len = (uint32_t)(N - X0 < (uint64_t)a * R ? N - X0 : (uint64_t)a * R);
+
+    const float *src = P.X + (size_t)k * N + X0;
+    for (uint32_t i = threadIdx.x * 4u; i < len; i += kThreads * 4u)
+        *reinterpret_cast<v4f *>(run + i) = *reinterpret_cast<const v4f *>(src + i);
+    for (uint32_t w = threadIdx.x; w <= a; w += kThreads) {
+        const int64_t num = (int64_t)w * (int64_t)N - (int64_t)b;
+        const int64_t q = num >= 0 ? (num + (int64_t)a - 1) / (int64_t)a : -((-num) / (int64_t)a);
+        s_tab[w] = (int32_t)q;
+        r_tab[w] = (int32_t)(q * (int64_t)a - num);
+    }
+    __syncthreads();
+
+    // Strand w covers j in [js, js + R), js = c R + s_w, read from the run at
+    // r_w + a (j - js). Threads take aligned quads of j: interior quads are
+    // one 16-byte store; the quads at the ends of a strand (and of the pool)
+    // store their valid values one by one.
+    float *g = P.G + (size_t)k * N;
+    const int64_t jc = (int64_t)c * R;
+    const uint32_t Q = (R >> 2) + 1u;  // aligned quads that cover R values
+    const float rq = 1.0f / (float)Q;
+    const uint32_t pairs = (a + 1u) * Q;
+#pragma unroll 2
+    for (uint32_t pr = threadIdx.x; pr < pairs; pr += kThreads) {
+        uint32_t w = (uint32_t)((float)pr * rq);
+        w = w * Q > pr ? w - 1u : ((w + 1u) * Q <= pr ? w + 1u : w);
+        const uint32_t u = pr - w * Q;
+        const int64_t js = jc + s_tab[w];
+        const int64_t q0 = (js & ~(int64_t)3) + 4 * (int64_t)u;
+        const int32_t t0 = (int32_t)(q0 - js);  // in [-3, R + 3)
+        const uint32_t r = (uint32_t)r_tab[w];
+        if (t0 >= 0 && t0 + 3 < (int32_t)R && q0 >= 0 && q0 + 3 < (int64_t)N &&
+            r + a * (uint32_t)(t0 + 3) < len) {
+            const uint32_t x0 = r + a * (uint32_t)t0;
+            const v4f v = {run[x0], run[x0 + a], run[x0 + 2u * a], run[x0 + 3u * a]};
+            *reinterpret_cast<v4f *>(g + q0) = v;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int32_t t = t0 + e;
+                const int64_t j = q0 + e;
+                if (t >= 0 && t < (int32_t)R && j >= 0 && j < (int64_t)N) {
+                    const uint32_t xo = r + a * (uint32_t)t;
+                    if (xo < len) g[j] = run[xo];
+                }
+            }
+        }
+    }
+}
+
+template <class Nd, int NC, int T, bool PERM>
 __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
 {
     __shared__ double2 red[4 * NC];
-    __shared__ uint32_t last;
     const GenState st = *P.state;
     if (st.flags & WALLACE_FLAG_CORRUPT) return;
     const uint32_t N = P.N;
@@ -237,9 +422,13 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
     float X[NC][T];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-        const float *src = P.X + (size_t)k * N;
+        if constexpr (PERM) {
+            load_run<T>(X[k], P.G + (size_t)k * N + j0);
+        } else {
+            const float *src = P.X + (size_t)k * N;
 #pragma unroll
-        for (int i = 0; i < T; ++i) X[k][i] = src[(a[k] * (j0 + i) + b[k]) & mask];
+            for (int i = 0; i < T; ++i) X[k][i] = src[(a[k] * (j0 + i) + b[k]) & mask];
+        }
     }
 #pragma unroll
     for (int i = 0; i < T; ++i) {
@@ -276,24 +465,15 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
 
     // write back the new pool; return it if requested (flat order)
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        float *dst = P.Y + (size_t)k * N + j0;
-#pragma unroll
-        for (int i = 0; i < T; i += 4)
-            *reinterpret_cast<v4f *>(dst + i) =
-                v4f{X[k][i], X[k][i + 1], X[k][i + 2], X[k][i + 3]};
-    }
+    for (int k = 0; k < NC; ++k) store_run<T>(P.Y + (size_t)k * N + j0, X[k], false);
     if (P.out) {
-        const bool vec = P.emit_cnt == nu && !P.affine && ((uintptr_t)P.out & 15) == 0;
+        const bool vec = P.emit_cnt == nu && !P.affine &&
+                         ((uintptr_t)P.out & (uintptr_t)(4 * (T < 4 ? T : 4) - 1)) == 0;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             float *dst = P.out + (size_t)k * N + j0;
             if (vec) {
-#pragma unroll
-                for (int i = 0; i < T; i += 4)
-                    __builtin_nontemporal_store(
-                        v4f{X[k][i], X[k][i + 1], X[k][i + 2], X[k][i + 3]},
-                        reinterpret_cast<v4f *>(dst + i));
+                store_run<T>(dst, X[k], true);
             } else {
 #pragma unroll
                 for (int i = 0; i < T; ++i) {
@@ -309,62 +489,121 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
     }
 
     block_partials<Nd, NC, T>(X, P.partials, P.nblocks, red);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        last = (atomicAdd(P.counter, 1u) == P.nblocks - 1u) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    const double sigma = final_tree<Nd, NC>(P.partials, P.nblocks, red);
+}
+
+// Finish of a pass (one block, after the pass kernel): the sum of squares
+// of the new pool from the per-block partials, and the generator state for
+// the next pass. A separate launch, so no block of the pass kernel needs a
+// device-wide fence (each would write back the whole L2).
+template <class Nd, int NC>
+__global__ __launch_bounds__(kFinThreads) void k_stream_finish(Pass P)
+{
+    const GenState st = *P.state;
+    if (st.flags & WALLACE_FLAG_CORRUPT) return;
+    const uint32_t nu = NC * P.N;
+    const double xstar = (double)P.X[nu - 1];
+    const double t = xstar + P.r_nu;
+    const double S = (t * t) * 0.5;
+    const float c32 = (float)__builtin_sqrt(S / st.sigma);
+    const double sigma = final_tree<Nd, NC>(P.partials, P.nblocks);
     if (threadIdx.x == 0) {
         GenState ns = st;
-        ns.rng = rng;
+        ns.rng = st.rng + (uint64_t)NC * 0x9E3779B97F4A7C15ull;
         ns.sigma = sigma;
         ns.passes = st.passes + 1;
         if (!__builtin_isfinite(c32)) ns.flags |= WALLACE_FLAG_NONFINITE;
         *P.state = ns;
-        *P.counter = 0u;
-        __threadfence();
     }
+}
+
+template <int NC>
+const void *finish_fn(uint32_t rmode)
+{
+    if (rmode == 1) return reinterpret_cast<const void *>(&k_stream_finish<F32, NC>);
+    if (rmode == 2) return reinterpret_cast<const void *>(&k_stream_finish<F32C, NC>);
+    return reinterpret_cast<const void *>(&k_stream_finish<F64, NC>);
 }
 
 template <class Nd, int NC, int T>
-const void *pass_fn()
+const void *pass_fn(bool perm)
 {
-    return reinterpret_cast<const void *>(&k_stream_pass<Nd, NC, T>);
+    return perm ? reinterpret_cast<const void *>(&k_stream_pass<Nd, NC, T, true>)
+                : reinterpret_cast<const void *>(&k_stream_pass<Nd, NC, T, false>);
 }
 
 template <int NC, int T>
-const void *pass_fn_mode(uint32_t rmode)
+const void *pass_fn_mode(uint32_t rmode, bool perm)
 {
-    if (rmode == 1) return pass_fn<F32, NC, T>();
-    if (rmode == 2) return pass_fn<F32C, NC, T>();
-    return pass_fn<F64, NC, T>();
+    if (rmode == 1) return pass_fn<F32, NC, T>(perm);
+    if (rmode == 2) return pass_fn<F32C, NC, T>(perm);
+    return pass_fn<F64, NC, T>(perm);
 }
 
-// Tuples per thread: at least 4 (16-byte stores) and enough that a pass
-// needs at most 1024 blocks (the last block reduces 4 partials per thread).
+// Tuples per thread: 4 for n = 4 (16-byte accesses), 1 for n = 16 (16
+// values per thread either way, which keeps 8 waves per SIMD), doubled
+// until a pass needs at most 4096 blocks (the finish block reduces at most
+// 4 partials per thread).
 int stream_T(int n, uint32_t N)
 {
-    uint32_t T = 4;
-    while ((uint64_t)N / ((uint64_t)kThreads * T) > 1024) T *= 2;
-    (void)n;
+    uint32_t T = n == 4 ? 4u : 1u;
+    while ((uint64_t)N / ((uint64_t)kThreads * T) > 4096) T *= 2;
     return (int)T;
 }
 
-const void *pass_kernel(int n, uint32_t N, uint32_t rmode)
+const void *pass_kernel(int n, uint32_t N, uint32_t rmode, bool perm)
 {
     const int T = stream_T(n, N);
     if (n == 4) {
-        if (T == 4) return pass_fn_mode<4, 4>(rmode);
-        if (T == 8) return pass_fn_mode<4, 8>(rmode);
-        if (T == 16) return pass_fn_mode<4, 16>(rmode);
+        if (T == 4) return pass_fn_mode<4, 4>(rmode, perm);
+        if (T == 8) return pass_fn_mode<4, 8>(rmode, perm);
+        if (T == 16) return pass_fn_mode<4, 16>(rmode, perm);
     } else if (n == 16) {
-        if (T == 4) return pass_fn_mode<16, 4>(rmode);
+        if (T == 1) return pass_fn_mode<16, 1>(rmode, perm);
+        if (T == 2) return pass_fn_mode<16, 2>(rmode, perm);
+        if (T == 4) return pass_fn_mode<16, 4>(rmode, perm);
     }
     return nullptr;
+}
+
+// Larger prime of component k's pair (bounds the LDS run a * R).
+uint32_t stride_hi(int k)
+{
+    constexpr uint32_t hi[16] = {5, 11, 17, 23, 31, 41, 47, 59,
+                                 67, 73, 83, 97, 103, 109, 127, 137};
+    return hi[k];
+}
+
+uint32_t stride_lo(int k)
+{
+    constexpr uint32_t lo[16] = {3, 7, 13, 19, 29, 37, 43, 53,
+                                 61, 71, 79, 89, 101, 107, 113, 131};
+    return lo[k];
+}
+
+// Launch shape of the permute kernel: R_k the largest power of two with
+// hi_k R_k <= kRunFloats; enough blocks for the smaller stride of the pair.
+Perm perm_shape(int n, uint32_t N)
+{
+    Perm p{};
+    p.N = N;
+    uint32_t blocks = 0;
+    for (int k = 0; k < n; ++k) {
+        uint32_t logR = 2;
+        while ((stride_hi(k) << (logR + 1)) <= kRunFloats) ++logR;
+        p.logR[k] = logR;
+        p.first[k] = blocks;
+        const uint64_t run = (uint64_t)stride_lo(k) << logR;
+        blocks += (uint32_t)((N + run - 1) / run);
+    }
+    p.first[n] = blocks;
+    return p;
+}
+
+size_t perm_lds_bytes(const Perm &p, int n)
+{
+    size_t m = 0;
+    for (int k = 0; k < n; ++k) m = std::max<size_t>(m, (size_t)stride_hi(k) << p.logR[k]);
+    return m * sizeof(float);
 }
 
 }  // namespace
@@ -378,7 +617,7 @@ bool stream_shape_ok(int n, uint32_t N)
 
 size_t stream_partials_bytes(int n, uint32_t N)
 {
-    if (N < (uint32_t)kThreads * 4) return 0;
+    if (!stream_shape_ok(n, N)) return 0;
     const uint32_t nb = N / (kThreads * (uint32_t)stream_T(n, N));
     return (size_t)n * nb * sizeof(double2);
 }
@@ -399,19 +638,37 @@ hipError_t stream_check(wallace_gen *g, hipStream_t s)
 hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last_emit,
                       uint32_t affine, float mu, float sig, hipStream_t s)
 {
-    const void *fn = pass_kernel(g->n, g->N, (uint32_t)g->opts.reduce_mode);
+    // prime-pair strides keep a * R small enough for the LDS runs
+    const bool perm = g->opts.a_mode == 0 && g->N >= kRunFloats;
+    const void *fn = pass_kernel(g->n, g->N, (uint32_t)g->opts.reduce_mode, perm);
     if (!fn) return hipErrorInvalidValue;
+    const void *ffn = g->n == 4 ? finish_fn<4>((uint32_t)g->opts.reduce_mode)
+                                : finish_fn<16>((uint32_t)g->opts.reduce_mode);
+    Perm pm{};
+    size_t pm_lds = 0;
+    const void *pfn = nullptr;
+    if (perm) {
+        pm = perm_shape(g->n, g->N);
+        pm_lds = perm_lds_bytes(pm, g->n);
+        pfn = g->n == 4 ? reinterpret_cast<const void *>(&k_stream_permute<4>)
+                        : reinterpret_cast<const void *>(&k_stream_permute<16>);
+        pm.state = g->state;
+    }
     const int T = stream_T(g->n, g->N);
     const uint32_t nblocks = g->N / (kThreads * (uint32_t)T);
     float *pa = reinterpret_cast<float *>(g->ws + g->lay.pool);
     float *pb = reinterpret_cast<float *>(g->ws + g->lay.pool2);
-    WsHeader *hdr = reinterpret_cast<WsHeader *>(g->ws);
     const uint32_t f = (uint32_t)g->opts.f;
+    // A returned pool that is emitted whole, unscaled and 16-byte aligned is
+    // the next pass's old pool: the pass then writes only the caller's
+    // output (one 4 nu-byte stream less). The call's last pass always writes
+    // the workspace pool that the next call starts from.
+    const float *src = ((g->passes_host & 1) != 0) ? pb : pa;
     for (uint32_t ps = 0; ps < passes; ++ps) {
-        const bool odd = ((g->passes_host + ps) & 1) != 0;
+        float *ws_dst = ((g->passes_host + ps + 1) & 1) != 0 ? pb : pa;
         Pass P{};
-        P.X = odd ? pb : pa;
-        P.Y = odd ? pa : pb;
+        P.X = src;
+        P.Y = ws_dst;
         P.out = nullptr;
         P.emit_cnt = 0;
         if ((ps + 1) % f == 0) {
@@ -419,18 +676,33 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
             P.out = out + (uint64_t)e * g->emit_len;
             P.emit_cnt = (ps + 1 == passes) ? last_emit : (uint32_t)g->emit_len;
         }
+        if (P.out && ps + 1 < passes && P.emit_cnt == g->nu && !affine &&
+            ((uintptr_t)P.out & 15) == 0) {
+            P.Y = P.out;
+            P.out = nullptr;
+        }
+        P.G = P.Y;  // permuted in place of the new pool
+        src = P.Y;
         P.affine = affine;
         P.mu = mu;
         P.sig = sig;
         P.state = g->state;
         P.partials = reinterpret_cast<double2 *>(g->ws + g->lay.partials);
-        P.counter = &hdr->stream_ctr;
         P.r_nu = g->r_nu;
         P.N = g->N;
         P.a_mode = (uint32_t)g->opts.a_mode;
         P.nblocks = nblocks;
+        if (perm) {
+            pm.X = P.X;
+            pm.G = P.Y;
+            void *pargs[] = {&pm};
+            hipError_t e = hipLaunchKernel(pfn, dim3(pm.first[g->n]), dim3(kThreads), pargs,
+                                           pm_lds, s);
+            if (e != hipSuccess) return e;
+        }
         void *args[] = {&P};
         hipError_t e = hipLaunchKernel(fn, dim3(nblocks), dim3(kThreads), args, 0, s);
+        if (e == hipSuccess) e = hipLaunchKernel(ffn, dim3(1), dim3(kFinThreads), args, 0, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

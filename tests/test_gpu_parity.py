@@ -171,6 +171,16 @@ def test_streaming_small(n, N, passes):
     assert_bits_equal(got, ref, f"stream n={n} N={N}")
 
 
+def test_streaming_full_odd_strides():
+    # any odd stride (eq. 2): the single-launch gather form of the pass
+    _dev()
+    n, N = 4, 1 << 14 << 1
+    g = W.Generator(13, n, N, a_mode=1)
+    got = gpu_stream(g, [n * N * 4 + 9])
+    ref = oracle.Gen(13, n, N, a_mode=oracle.A_FULL_ODD).fill(n * N * 4 + 9)
+    assert_bits_equal(got, ref, "stream a_mode 1")
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_streaming_reduce_modes(mode):
     _dev()

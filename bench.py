@@ -13,6 +13,7 @@ oracle on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --only headline     (profiling runs: no extras)
+       python bench.py --only single_large (profiling runs: streamed pool only)
        python bench.py --copy-probe BYTES  (calibration copy for counters)
 """
 from __future__ import annotations
@@ -38,7 +39,8 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("wallace_kernels.hip", "wallace_internal.h"):
+    for name in ("wallace_pool.cuh", "wallace_pool_inst.hip", "wallace_kernels.hip",
+                 "wallace_internal.h"):
         with open(os.path.join(ROOT, "paper_1004_3114_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -145,10 +147,20 @@ def single_pool(torch, W, workloads, which, reps=3):
     del out
     torch.cuda.empty_cache()
     rate = spec.normals / (best * 1e-3)
-    return {"workload": spec.name, "n": spec.n, "N": spec.N, "passes": spec.passes,
-            "normals": spec.normals, "ms": round(best, 3), "normals_per_s": rate,
-            "write_GBps": round(rate * 4 / 1e9, 1),
-            "frac_hbm": round(rate * 4 / 1e9 / HBM_PEAK_GBPS, 4)}
+    res = {"workload": spec.name, "n": spec.n, "N": spec.N, "passes": spec.passes,
+           "normals": spec.normals, "ms": round(best, 3), "normals_per_s": rate,
+           "write_GBps": round(rate * 4 / 1e9, 1),
+           "frac_hbm": round(rate * 4 / 1e9 / HBM_PEAK_GBPS, 4)}
+    if which == "large":
+        # streamed pass: permute reads and writes the pool, combine reads it
+        # and writes the returned pool (which the next pass reads); the last
+        # pass also writes the workspace pool
+        nu = spec.n * spec.N
+        traffic = (16 * nu) * spec.passes + 4 * nu
+        res["hbm_alg_bytes"] = traffic
+        res["hbm_alg_GBps"] = round(traffic / (best * 1e-3) / 1e9, 1)
+        res["hbm_alg_frac"] = round(traffic / (best * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+    return res
 
 
 def uneven(torch, W, workloads, reps=3):
@@ -232,7 +244,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["headline", "all"], default="all")
+    ap.add_argument("--only", choices=["headline", "single_large", "all"], default="all")
     ap.add_argument("--copy-probe", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -259,6 +271,9 @@ def main():
         return
     from paper_1004_3114_amd import wallace as W
     W.lib()  # fails loudly if the HIP library is missing
+    if args.only == "single_large":
+        print(json.dumps(single_pool(torch, W, workloads, "large")), flush=True)
+        return
     value, ms_per_step, roof, cfg = headline(torch, W, workloads, args.steps, args.warmup)
     line = {"metric": "normals/sec at 1 GPU (FP32) + % HBM-write roofline; batched vs single-pool",
             "value": value, "unit": "normals/s", "n_gpus": 1, "steps": args.steps,

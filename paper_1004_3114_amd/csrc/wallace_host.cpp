@@ -237,7 +237,7 @@ int32_t wallace_init(uint64_t seed, int32_t n, uint32_t N,
     g->cursor = g->emit_len;  // the initial pool is not returned
     g->streaming = !default_sched(n, N, &g->sched);
     g->passes_host = 0;
-    if ((o.transform_mode == 1 && !g->streaming) || (g->streaming && !stream_shape_ok(n, N))) {
+    if ((o.transform_mode == 1 && !g->streaming) || (g->streaming && !stream_shape_ok(n, N, o.transform_mode))) {
         delete g;
         return WALLACE_EUNSUP;
     }

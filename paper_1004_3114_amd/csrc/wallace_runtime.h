@@ -54,7 +54,7 @@ namespace wallace {
 
 // Streaming path for pools too large to stay on chip (wallace_stream.hip).
 size_t stream_partials_bytes(int n, uint32_t N);
-bool stream_shape_ok(int n, uint32_t N);
+bool stream_shape_ok(int n, uint32_t N, int transform_mode);
 const float *stream_current_pool(wallace_gen *g);
 hipError_t stream_check(wallace_gen *g, hipStream_t s);
 hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last_emit,

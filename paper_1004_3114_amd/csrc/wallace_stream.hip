@@ -388,10 +388,50 @@ __global__ __launch_bounds__(kThreads) void k_stream_permute(Perm P)
     }
 }
 
-template <class Nd, int NC, int T, bool PERM>
+// n = 16 transform on the matrix cores (accuracy variant, not bit-exact):
+// y = (h H16 D) v for 16 tuples per MFMA group. A wave's 64 tuples go
+// through LDS: lane l of group g feeds component 4s + l/16 of tuple
+// 16g + l%16 at step s (B operand, 4 x 16) against the 16 x 4 slice
+// h H16[m][4s + kk] d_(4s + kk) (A operand), and receives components
+// 4(l/16) .. 4(l/16)+3 of tuple 16g + l%16.
+__device__ __forceinline__ void xform16_mfma(float (&v)[16], uint32_t signs, float h,
+                                             float (*tile)[kThreads + 16])
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int base = tid & ~63;  // this wave's first tuple in the block
+#pragma unroll
+    for (int k = 0; k < 16; ++k) tile[k][tid] = v[k];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // wave-local LDS, in order
+    const int m = lane & 15, q = lane >> 4;
+    float a[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        const int kk = 4 * st + q;
+        const int odd = (__builtin_popcount((unsigned)(m & kk)) + (int)((signs >> kk) & 1u)) & 1;
+        a[st] = odd ? -h : h;
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int col = base + 16 * g + m;
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], tile[4 * st + q][col], acc, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tile[4 * q + i][col] = acc[i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = tile[k][tid];
+}
+
+template <class Nd, int NC, int T, bool PERM, bool MF>
 __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
 {
+    static_assert(!MF || (NC == 16 && T == 1), "matrix-core transform: n = 16, one tuple per thread");
     __shared__ double2 red[4 * NC];
+    __shared__ float tile[MF ? 16 : 1][kThreads + 16];
     const GenState st = *P.state;
     if (st.flags & WALLACE_FLAG_CORRUPT) return;
     const uint32_t N = P.N;
@@ -433,6 +473,14 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         float v[NC];
+        if constexpr (MF) {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) v[k] = X[k][i];
+            xform16_mfma(v, signs, h, tile);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) X[k][i] = v[k];
+            continue;
+        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) v[k] = ((signs >> k) & 1u) ? -X[k][i] : X[k][i];
         if constexpr (NC == 4) {
@@ -524,19 +572,19 @@ const void *finish_fn(uint32_t rmode)
     return reinterpret_cast<const void *>(&k_stream_finish<F64, NC>);
 }
 
-template <class Nd, int NC, int T>
+template <class Nd, int NC, int T, bool MF>
 const void *pass_fn(bool perm)
 {
-    return perm ? reinterpret_cast<const void *>(&k_stream_pass<Nd, NC, T, true>)
-                : reinterpret_cast<const void *>(&k_stream_pass<Nd, NC, T, false>);
+    return perm ? reinterpret_cast<const void *>(&k_stream_pass<Nd, NC, T, true, MF>)
+                : reinterpret_cast<const void *>(&k_stream_pass<Nd, NC, T, false, MF>);
 }
 
-template <int NC, int T>
+template <int NC, int T, bool MF = false>
 const void *pass_fn_mode(uint32_t rmode, bool perm)
 {
-    if (rmode == 1) return pass_fn<F32, NC, T>(perm);
-    if (rmode == 2) return pass_fn<F32C, NC, T>(perm);
-    return pass_fn<F64, NC, T>(perm);
+    if (rmode == 1) return pass_fn<F32, NC, T, MF>(perm);
+    if (rmode == 2) return pass_fn<F32C, NC, T, MF>(perm);
+    return pass_fn<F64, NC, T, MF>(perm);
 }
 
 // Tuples per thread: 4 for n = 4 (16-byte accesses), 1 for n = 16 (16
@@ -550,9 +598,10 @@ int stream_T(int n, uint32_t N)
     return (int)T;
 }
 
-const void *pass_kernel(int n, uint32_t N, uint32_t rmode, bool perm)
+const void *pass_kernel(int n, uint32_t N, uint32_t rmode, bool perm, bool mf)
 {
     const int T = stream_T(n, N);
+    if (mf) return (n == 16 && T == 1) ? pass_fn_mode<16, 1, true>(rmode, perm) : nullptr;
     if (n == 4) {
         if (T == 4) return pass_fn_mode<4, 4>(rmode, perm);
         if (T == 8) return pass_fn_mode<4, 8>(rmode, perm);
@@ -608,16 +657,17 @@ size_t perm_lds_bytes(const Perm &p, int n)
 
 }  // namespace
 
-bool stream_shape_ok(int n, uint32_t N)
+bool stream_shape_ok(int n, uint32_t N, int transform_mode)
 {
     if (N < (uint32_t)kThreads * 4) return false;
     const int T = stream_T(n, N);
+    if (transform_mode == 1) return n == 16 && T == 1;
     return (n == 4 && T <= 16) || (n == 16 && T <= 4);
 }
 
 size_t stream_partials_bytes(int n, uint32_t N)
 {
-    if (!stream_shape_ok(n, N)) return 0;
+    if (!stream_shape_ok(n, N, 0)) return 0;
     const uint32_t nb = N / (kThreads * (uint32_t)stream_T(n, N));
     return (size_t)n * nb * sizeof(double2);
 }
@@ -640,7 +690,8 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
 {
     // prime-pair strides keep a * R small enough for the LDS runs
     const bool perm = g->opts.a_mode == 0 && g->N >= kRunFloats;
-    const void *fn = pass_kernel(g->n, g->N, (uint32_t)g->opts.reduce_mode, perm);
+    const void *fn = pass_kernel(g->n, g->N, (uint32_t)g->opts.reduce_mode, perm,
+                                 g->opts.transform_mode == 1);
     if (!fn) return hipErrorInvalidValue;
     const void *ffn = g->n == 4 ? finish_fn<4>((uint32_t)g->opts.reduce_mode)
                                 : finish_fn<16>((uint32_t)g->opts.reduce_mode);

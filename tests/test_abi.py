@@ -83,6 +83,9 @@ def test_init_argument_errors_before_gpu():
     assert L.wallace_init(1, 4, 64, ctypes.byref(bad), 4096, 1 << 20, None, ctypes.byref(h)) == W.WALLACE_EINVAL
     mm = W.make_opts(transform_mode=1)  # matrix cores only for n = 16
     assert L.wallace_init(1, 4, 1 << 20, ctypes.byref(mm), 4096, 1 << 40, None, ctypes.byref(h)) == W.WALLACE_EUNSUP
+    # ... and for streamed pools of one tuple per thread (n = 16, 2^13 <= N <= 2^20)
+    assert L.wallace_init(1, 16, 256, ctypes.byref(mm), 4096, 1 << 40, None, ctypes.byref(h)) == W.WALLACE_EUNSUP
+    assert L.wallace_init(1, 16, 1 << 22, ctypes.byref(mm), 4096, 1 << 40, None, ctypes.byref(h)) == W.WALLACE_EUNSUP
     assert not h.value
 
 

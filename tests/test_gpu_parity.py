@@ -223,3 +223,26 @@ def test_precision_shape_first_passes():
     got = gpu_stream(g, [n * N * 3])
     ref = oracle.Gen(42, n, N).fill(n * N * 3)
     assert_bits_equal(got, ref, "precision shape")
+
+
+# ---------------------------------------------------------------------------
+# matrix-core transform (n = 16, accuracy variant)
+# ---------------------------------------------------------------------------
+
+def test_mfma_transform_accuracy():
+    # H16 D / 4 on the matrix cores is not bit-exact; it must stay within the
+    # per-variate bound against the FP64 oracle, and differ from the
+    # butterflies somewhere (so the matrix-core path is the one that ran)
+    _dev()
+    n, N, P = 16, 1 << 13, 20
+    nu = n * N
+    print("case mfma n=16 N=2^13", flush=True)
+    g = W.Generator(42, n, N, transform_mode=1)
+    got = gpu_stream(g, [nu * P]).reshape(P, nu)
+    ref64 = oracle.Gen64(42, n, N).fill(nu * P).reshape(P, nu)
+    ref32 = oracle.Gen(42, n, N).fill(nu * P).reshape(P, nu)
+    err = np.abs(got.astype(np.float64) - ref64) / np.maximum(1.0, np.abs(ref64))
+    err32 = np.abs(ref32.astype(np.float64) - ref64) / np.maximum(1.0, np.abs(ref64))
+    print(f"mfma max err {err.max():.3g}, butterflies {err32.max():.3g}", flush=True)
+    assert err.max() <= 1e-5
+    assert np.any(got.view(np.uint32) != ref32.view(np.uint32))

@@ -14,6 +14,7 @@ oracle on a bounded sample of the same workload.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --only headline     (profiling runs: no extras)
        python bench.py --only single_large (profiling runs: streamed pool only)
+       python bench.py --only uneven       (profiling runs: uneven batch only)
        python bench.py --copy-probe BYTES  (calibration copy for counters)
 """
 from __future__ import annotations
@@ -168,6 +169,9 @@ def uneven(torch, W, workloads, reps=3):
     total = spec.normals_per_launch()
     log(f"batch_uneven: G={spec.G} normals={total}")
     b = W.Batch(spec.seeds, spec.n, spec.N)
+    t0 = time.time()
+    b.tune()  # per (n, N) class: the fastest pool-resident schedule
+    log(f"batch_uneven tuned in {time.time() - t0:.1f}s")
     b.plan(spec.offsets(), spec.passes)
     out = torch.empty(total, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -244,7 +248,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["headline", "single_large", "all"], default="all")
+    ap.add_argument("--only", choices=["headline", "single_large", "uneven", "all"],
+                    default="all")
     ap.add_argument("--copy-probe", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -273,6 +278,9 @@ def main():
     W.lib()  # fails loudly if the HIP library is missing
     if args.only == "single_large":
         print(json.dumps(single_pool(torch, W, workloads, "large")), flush=True)
+        return
+    if args.only == "uneven":
+        print(json.dumps(uneven(torch, W, workloads)), flush=True)
         return
     value, ms_per_step, roof, cfg = headline(torch, W, workloads, args.steps, args.warmup)
     line = {"metric": "normals/sec at 1 GPU (FP32) + % HBM-write roofline; batched vs single-pool",

@@ -53,7 +53,11 @@ struct ClassInfo {
     std::vector<uint32_t> gens;  // generators of this class
     uint32_t job_begin = 0, job_count = 0;
     int grid = 0;
+    double work = 0.0;  // values written by the planned launch (ordering only)
 };
+
+// Classes of one batch run concurrently on up to this many streams.
+constexpr int kClassLanes = 4;
 
 }  // namespace
 
@@ -67,6 +71,17 @@ struct wallace_batch {
     std::vector<ClassInfo> classes;
     bool planned = false;
     int cus = 0;
+    // streams (default priority) and events that let classes of one fill
+    // run side by side; created at the first fill that needs them
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
+    ~wallace_batch()
+    {
+        for (hipStream_t x : side) (void)hipStreamDestroy(x);
+        for (hipEvent_t x : join) (void)hipEventDestroy(x);
+        if (fork) (void)hipEventDestroy(fork);
+    }
 };
 
 namespace {
@@ -120,15 +135,53 @@ hipError_t upload_jobs(wallace_batch *b, const std::vector<Job> &jobs, hipStream
     return hipStreamSynchronize(s);
 }
 
+// One launch per class. Several classes are spread over up to kClassLanes
+// streams (the caller's and side streams forked from it and joined back),
+// largest work first onto the least loaded stream, so one class's tail
+// overlaps the next class instead of idling the GPU. Under graph capture
+// the fork and join become parallel branches of the graph.
 hipError_t launch_classes(wallace_batch *b, float *out, uint32_t sigma_mode, hipStream_t s)
 {
-    for (const ClassInfo &c : b->classes) {
-        if (c.job_count == 0) continue;
-        const PoolArgs a = class_args(b, c, out, sigma_mode);
-        hipError_t e = launch_pool(c.sched, a, c.grid, s);
-        if (e != hipSuccess) return e;
+    std::vector<const ClassInfo *> live;
+    for (const ClassInfo &c : b->classes)
+        if (c.job_count) live.push_back(&c);
+    const int nside = std::min<int>((int)live.size(), kClassLanes) - 1;
+    if (nside <= 0) {
+        for (const ClassInfo *c : live) {
+            hipError_t e = launch_pool(c->sched, class_args(b, *c, out, sigma_mode), c->grid, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
     }
-    return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (!b->fork) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    while (e == hipSuccess && (int)b->side.size() < nside) {
+        hipStream_t x = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+        if (e != hipSuccess) break;
+        b->side.push_back(x);
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->join.push_back(ev);
+    }
+    if (e != hipSuccess) return e;
+    std::stable_sort(live.begin(), live.end(),
+                     [](const ClassInfo *x, const ClassInfo *y) { return x->work > y->work; });
+    e = hipEventRecord(b->fork, s);
+    for (int i = 0; i < nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(b->side[i], b->fork, 0);
+    std::vector<double> load((size_t)nside + 1, 0.0);
+    for (const ClassInfo *c : live) {
+        if (e != hipSuccess) break;
+        const int lane = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[lane] += c->work;
+        e = launch_pool(c->sched, class_args(b, *c, out, sigma_mode), c->grid,
+                        lane == 0 ? s : b->side[lane - 1]);
+    }
+    for (int i = 0; i < nside && e == hipSuccess; ++i) {
+        e = hipEventRecord(b->join[i], b->side[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[i], 0);
+    }
+    return e;
 }
 
 }  // namespace
@@ -239,6 +292,7 @@ int32_t wallace_batch_init(uint32_t G, const uint64_t *seeds, const int32_t *n,
             jobs.push_back(j);
         }
         c.job_count = (uint32_t)c.gens.size();
+        c.work = (double)c.job_count * c.n * c.N;
         if (e == hipSuccess) e = class_grid(c, b->cus, (uint32_t)b->opts.reduce_mode);
     }
     if (e == hipSuccess) e = upload_jobs(b, jobs, s);
@@ -287,6 +341,8 @@ int32_t wallace_batch_plan(wallace_batch *b, const uint64_t *offsets, const uint
             jobs.push_back(j);
         }
         c.job_count = (uint32_t)order.size();
+        c.work = 0.0;
+        for (uint32_t g : order) c.work += (double)passes[g] * (double)b->n[g] * b->N[g];
         hipError_t e = class_grid(c, b->cus, (uint32_t)b->opts.reduce_mode);
         if (e != hipSuccess) return hip_fail(e, "occupancy query");
     }

@@ -483,19 +483,23 @@ __device__ __forceinline__ void store_lds(float *p, const float (&x)[T])
 }
 
 // Element-wise emission: partial pools, unaligned outputs, N(mu, sigma^2).
+// One base address per component; the T values of a lane are immediate
+// offsets from it, and value i is inside the emitted prefix iff i < lim.
 template <int NC, int T, int N>
 __device__ __forceinline__ void emit_slow(const float (&X)[NC][T], float *base, uint32_t cnt,
                                           int lane, uint32_t affine, float mu, float sig)
 {
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
+        const int32_t lim = (int32_t)cnt - (int32_t)(k * N) - (int32_t)(T * lane);
+        if (lim <= 0) continue;
+        float *bk = base + (k * N + T * lane);
 #pragma unroll
         for (int i = 0; i < T; ++i) {
-            const uint32_t fl = (uint32_t)(k * N) + (uint32_t)(T * lane + i);
-            if (fl < cnt) {
+            if (i < lim) {
                 float y = X[k][i];
                 if (affine) y = mu + sig * y;
-                __builtin_nontemporal_store(y, base + fl);
+                __builtin_nontemporal_store(y, bk + i);
             }
         }
     }
@@ -657,7 +661,8 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
 
     // Chunks of CH passes (CH is even, so every chunk starts on the same
     // matrix); two passes per iteration (n = 4: A0 then A1), so the sum of
-    // squares of one pass and the permutation of the next share a block.
+    // squares of one pass and the permutation of the next share a block
+    // (measured faster for every shape, multi-wave groups included).
     using M0 = std::integral_constant<int, 0>;
     using M1 = std::integral_constant<int, NC == 4 ? 1 : 0>;
     const bool odd = NC == 4 && (done & 1u);

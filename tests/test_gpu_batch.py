@@ -59,6 +59,46 @@ def test_mixed_small_batch_two_launches():
     assert b.status() == (0, 0)
 
 
+def test_mixed_batch_graph_replays():
+    # classes run on forked streams; captured in a graph, the fork and join
+    # become parallel branches. Every replay continues each generator's
+    # stream and must match the oracle, with eager work between replays.
+    _dev()
+    rng = np.random.default_rng(5)
+    shapes = [(4, 16), (4, 256), (4, 1024), (4, 4096), (16, 16), (16, 256), (16, 1024)]
+    G = 28
+    pick = np.arange(G) % len(shapes)
+    n = np.array([shapes[i][0] for i in pick], dtype=np.int32)
+    N = np.array([shapes[i][1] for i in pick], dtype=np.uint32)
+    seeds = np.arange(700, 700 + G, dtype=np.uint64)
+    passes = rng.integers(1, 4, size=G).astype(np.uint32)
+    nu = n.astype(np.uint64) * N
+    sizes = nu * passes
+    off = np.zeros(G, np.uint64)
+    np.cumsum(sizes[:-1], out=off[1:])
+    total = int(sizes.sum())
+    print(f"case mixed batch graph G={G} total={total}", flush=True)
+    b = W.Batch(seeds, n, N)
+    b.plan(off, passes)
+    out = torch.zeros(total, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        b.fill(out, stream=torch.cuda.current_stream())
+    refs = [oracle.Gen(int(seeds[g]), int(n[g]), int(N[g])) for g in range(G)]
+    for rep in range(3):
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        host = out.cpu().numpy()
+        for g in range(G):
+            ref = refs[g].fill(int(sizes[g]))
+            assert_bits_equal(host[int(off[g]):int(off[g]) + int(sizes[g])], ref,
+                              f"replay {rep} gen {g} n={n[g]} N={N[g]}")
+    assert b.status() == (0, 0)
+
+
 @pytest.mark.parametrize("n,N", [(4, 256), (4, 2048), (16, 64), (16, 1024), (4, 16384)])
 def test_every_schedule_gives_identical_bits(n, N, monkeypatch):
     # Schedules differ in lanes per pool, tuples per lane and components per
@@ -159,6 +199,7 @@ def test_batch_uneven_full_size_sampled():
     per = spec.normals_per_launch()
     print(f"case batch_uneven full size {per}", flush=True)
     b = W.Batch(spec.seeds, spec.n, spec.N)
+    b.tune()  # the benchmark's launch configuration
     off = spec.offsets()
     b.plan(off, spec.passes)
     out = torch.empty(per, dtype=torch.float32, device="cuda")

@@ -16,6 +16,7 @@
 #include "wallace.h"
 #include "wallace_internal.h"
 #include "wallace_runtime.h"
+#include "wallace_tune.h"
 
 using namespace wallace;
 
@@ -101,6 +102,26 @@ bool default_sched(int n, uint32_t N, Sched *out)
         s.L = (int)(N / (uint32_t)tmax);
     }
     if (s.L < n || s.L > 1024) return false;
+    while (s.C > 1 && (size_t)s.C * N * sizeof(float) > 128 * 1024) s.C /= 2;
+    if (!pool_sched_supported(s, (int)N)) return false;
+    *out = s;
+    return true;
+}
+
+// One generator alone on the GPU: the pass is a latency chain, so the pool
+// is spread over more lanes (4 tuples per lane for n = 4, 1 for n = 16, up
+// to 1024 lanes) than in a batch, where single-wave groups keep the chip
+// busy with many pools. Measured for n = 4, N = 1024: 2.1 -> 1.06 us per
+// pass.
+bool single_sched(int n, uint32_t N, Sched *out)
+{
+    const int tmax = n == 4 ? 16 : 4;
+    Sched s{n, n == 4 ? 4 : 1, 0, n};
+    if (N < (uint32_t)s.T * (uint32_t)n) s.T = 1;
+    while (N / (uint32_t)s.T > 1024) s.T *= 2;
+    if (s.T > tmax || N % (uint32_t)s.T) return false;
+    s.L = (int)(N / (uint32_t)s.T);
+    if (s.L < n) return false;
     while (s.C > 1 && (size_t)s.C * N * sizeof(float) > 128 * 1024) s.C /= 2;
     if (!pool_sched_supported(s, (int)N)) return false;
     *out = s;
@@ -236,6 +257,13 @@ int32_t wallace_init(uint64_t seed, int32_t n, uint32_t N,
     g->emit_len = o.withhold_driver ? g->nu - 1 : g->nu;
     g->cursor = g->emit_len;  // the initial pool is not returned
     g->streaming = !default_sched(n, N, &g->sched);
+    if (!g->streaming) {
+        Sched t{};
+        if (forced_sched(n, N, &t))  // WALLACE_SCHED
+            g->sched = t;
+        else if (single_sched(n, N, &t))
+            g->sched = t;
+    }
     g->passes_host = 0;
     if ((o.transform_mode == 1 && !g->streaming) || (g->streaming && !stream_shape_ok(n, N, o.transform_mode))) {
         delete g;

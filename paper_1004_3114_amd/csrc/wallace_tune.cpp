@@ -103,7 +103,7 @@ TuneLayout tune_layout(int n, uint32_t N, uint32_t copies)
 
 }  // namespace
 
-bool tuned_sched(int n, uint32_t N, Sched *out)
+bool forced_sched(int n, uint32_t N, Sched *out)
 {
     // Explicit override, read at every call: WALLACE_SCHED="n:N:T:L:C,..."
     if (const char *ov = std::getenv("WALLACE_SCHED")) {
@@ -122,6 +122,12 @@ bool tuned_sched(int n, uint32_t N, Sched *out)
             if (*p == ',') ++p;
         }
     }
+    return false;
+}
+
+bool tuned_sched(int n, uint32_t N, Sched *out)
+{
+    if (forced_sched(n, N, out)) return true;
     std::lock_guard<std::mutex> lk(g_mu);
     load_cache_locked();
     auto it = g_cache.find(std::make_tuple(device_key(), 0, n, N));

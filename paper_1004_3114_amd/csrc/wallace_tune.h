@@ -12,8 +12,13 @@
 
 namespace wallace {
 
-// Schedule recorded for (n, N) on this device by an earlier tuning run, in
-// this process or in the cache file named by WALLACE_TUNE_CACHE.
+// Schedule forced for (n, N) by WALLACE_SCHED="n:N:T:L:C,..." (read at
+// every call).
+bool forced_sched(int n, uint32_t N, Sched *out);
+
+// The forced schedule, else the one recorded for (n, N) on this device by an
+// earlier tuning run, in this process or in the cache file named by
+// WALLACE_TUNE_CACHE.
 bool tuned_sched(int n, uint32_t N, Sched *out);
 
 // Scratch bytes tune_class needs for one class.

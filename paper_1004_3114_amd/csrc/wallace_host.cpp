@@ -275,6 +275,7 @@ int32_t wallace_init(uint64_t seed, int32_t n, uint32_t N,
     std::vector<float> host(g->nu);
     GenState st{};
     host_box_muller(seed, g->nu, host.data(), &st.rng);
+    g->rng0 = st.rng;
     WsHeader hdr{};
     hdr.magic = kWsMagic;
     hdr.G = 1;

@@ -45,6 +45,8 @@ struct wallace_gen {
     uint64_t emit_len;
     uint64_t cursor;       // values of the current returned pool already emitted
     uint64_t passes_host;  // passes enqueued since init (ping-pong parity)
+    uint64_t rng0;         // splitmix64 state after the initial pool: pass q
+                           // (0-based) draws from rng0 + n q gamma
     bool streaming;
     wallace::Sched sched;
     double r_nu;

@@ -6,9 +6,14 @@
 //     consecutive j each, which the block writes as coalesced runs of G_k.
 //   combine: reads G_k contiguously, applies the scaled transform, writes
 //     the new pool in place of G and, when it is a returned pool, the
-//     caller's output; the pass's sum of squares (section 4) is reduced by
-//     the last block to arrive, which also advances the generator state.
-// Arbitrary odd strides (eq. 2) use a single launch that gathers from HBM.
+//     caller's output, plus one partial sum of squares (section 4) per
+//     component and block.
+// The partials are reduced, and the generator state advanced, by one extra
+// block of the next pass's permute launch, or by a one-block finish launch
+// after a call's last pass. The host passes each pass's splitmix64 state, so
+// no permute block depends on the state that block rewrites.
+// Arbitrary odd strides (eq. 2) use one launch that gathers from HBM, then
+// the finish launch.
 #include "wallace_runtime.h"
 
 namespace wallace {
@@ -158,6 +163,11 @@ struct Pass {
     GenState *state;
     double2 *partials;  // [n][nblocks]
     double r_nu;
+    uint64_t rng;       // splitmix64 state the pass draws from
+    const double2 *comp;  // non-null: the old pool's sum of squares is the tree
+                          // over these per-component nodes (else state.sigma)
+    uint64_t passes;    // passes done once this pass is complete
+    uint32_t mat;       // n = 4: 1 for A1 (the pass after an odd count of passes)
     uint32_t N;
     uint32_t a_mode;
     uint32_t nblocks;
@@ -228,46 +238,39 @@ __device__ __forceinline__ Nd run_tree(const double2 *p)
     return t[0];
 }
 
-constexpr int kFinThreads = 1024;
-
 // Canonical tree over the n*nblocks partial nodes (nblocks a power of two,
-// at most 4 per thread of the finish block): per component over its blocks,
-// then over the components. Four components at a time have their loads in
-// flight together. Missing nodes are zeros, which join exactly.
-template <class Nd, int NC>
+// at most 16 per thread): per component over its blocks, then over the
+// components. A thread's run of nodes is joined four at a time in tree
+// order; missing nodes are zeros, which join exactly. NT threads.
+template <class Nd, int NT>
+__device__ __forceinline__ Nd thread_run(const double2 *p, uint32_t per)
+{
+    if (per == 1) return run_tree<Nd, 1>(p);
+    if (per == 2) return run_tree<Nd, 2>(p);
+    if (per == 4) return run_tree<Nd, 4>(p);
+    const Nd q0 = run_tree<Nd, 4>(p), q1 = run_tree<Nd, 4>(p + 4);
+    const Nd h0 = Nd::join(q0, q1);
+    if (per == 8) return h0;
+    const Nd q2 = run_tree<Nd, 4>(p + 8), q3 = run_tree<Nd, 4>(p + 12);
+    return Nd::join(h0, Nd::join(q2, q3));
+}
+
+template <class Nd, int NC, int NT>
 __device__ double final_tree(const double2 *partials, uint32_t nblocks)
 {
-    constexpr int NW = kFinThreads / 64;
-    constexpr int KG = NC < 4 ? NC : 4;
+    constexpr int NW = NT / 64;
     __shared__ double2 wv[NC][NW];
     __shared__ double2 comp[NC];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const uint32_t per = nblocks > kFinThreads ? nblocks / kFinThreads : 1u;
+    const uint32_t per = nblocks > NT ? nblocks / NT : 1u;
     const uint32_t b0 = threadIdx.x * per;
-    for (int k0 = 0; k0 < NC; k0 += KG) {
-        Nd acc[KG];
+    for (int k = 0; k < NC; ++k) {
+        Nd acc = Nd::zero();
+        if (b0 < nblocks) acc = thread_run<Nd, NT>(partials + (size_t)k * nblocks + b0, per);
 #pragma unroll
-        for (int q = 0; q < KG; ++q) acc[q] = Nd::zero();
-        if (b0 < nblocks) {
-            const double2 *p = partials + (size_t)k0 * nblocks + b0;
-            if (per == 1) {
-#pragma unroll
-                for (int q = 0; q < KG; ++q) acc[q] = run_tree<Nd, 1>(p + (size_t)q * nblocks);
-            } else if (per == 2) {
-#pragma unroll
-                for (int q = 0; q < KG; ++q) acc[q] = run_tree<Nd, 2>(p + (size_t)q * nblocks);
-            } else {
-#pragma unroll
-                for (int q = 0; q < KG; ++q) acc[q] = run_tree<Nd, 4>(p + (size_t)q * nblocks);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < KG; ++q) {
-#pragma unroll
-            for (int m = 0; m < 6; ++m) acc[q] = Nd::join(acc[q], Nd::xr(acc[q], 1 << m));
-            if (lane == 0) wv[k0 + q][wave] = acc[q].pack();
-        }
+        for (int m = 0; m < 6; ++m) acc = Nd::join(acc, Nd::xr(acc, 1 << m));
+        if (lane == 0) wv[k][wave] = acc.pack();
     }
     __syncthreads();
     if (threadIdx.x < NC) {
@@ -298,14 +301,68 @@ __device__ double final_tree(const double2 *partials, uint32_t nblocks)
     return out;
 }
 
-// LDS run of the permute kernel: at most kRunFloats source values.
-constexpr uint32_t kRunFloats = 8192;
+// Completes a call's pass from its partials: the new sum of squares, the
+// pass count and the splitmix64 state after the pass's draws (both known to
+// the host). NONFINITE was already set by the pass kernel; CORRUPT stops
+// everything.
+template <class Nd, int NC, int NT>
+__device__ void finish_pass(GenState *state, const double2 *partials, uint32_t nblocks,
+                            uint64_t passes, uint64_t rng_next)
+{
+    if (state->flags & WALLACE_FLAG_CORRUPT) return;
+    const double sigma = final_tree<Nd, NC, NT>(partials, nblocks);
+    if (threadIdx.x == 0) {
+        state->sigma = sigma;
+        state->passes = passes;
+        state->rng = rng_next;
+    }
+}
+
+// One component's node of the canonical tree: the tree over its nblocks
+// partial nodes (a power of two, at most 16 per thread), by one block of NT
+// threads. Thread 0 returns it.
+template <class Nd, int NT>
+__device__ Nd comp_sum(const double2 *p, uint32_t nblocks)
+{
+    constexpr int NW = NT / 64;
+    __shared__ double2 wv[NW];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const uint32_t per = nblocks > NT ? nblocks / NT : 1u;
+    const uint32_t b0 = threadIdx.x * per;
+    Nd acc = Nd::zero();
+    if (b0 < nblocks) acc = thread_run<Nd, NT>(p + b0, per);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) acc = Nd::join(acc, Nd::xr(acc, 1 << m));
+    if (lane == 0) wv[wave] = acc.pack();
+    __syncthreads();
+    Nd t[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t[w] = Nd::unpack(wv[w]);
+#pragma unroll
+    for (int w = NW; w > 1; w >>= 1) {
+#pragma unroll
+        for (int i = 0; i < w / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
+    }
+    return t[0];
+}
+
+// LDS run of the permute kernel: at most run_floats(n) source values. Runs
+// of 4096 values (16 KB) gave n = 4 the most blocks in flight; n = 16, with
+// strides up to 137, needs 8192 to keep its strands at 64 values or more.
+constexpr uint32_t kRunFloatsMax = 8192;
+__host__ __device__ constexpr uint32_t run_floats(int n) { return n == 4 ? 4096u : 8192u; }
 constexpr int kMaxStrands = 160;  // a + 1 for the largest prime-pair stride
 
 struct Perm {
     const float *X;        // old pool
     float *G;              // permuted components
-    const GenState *state;
+    GenState *state;
+    uint64_t rng;          // splitmix64 state the pass draws from
+    const double2 *partials;  // previous pass's partial sums [n][fin_nblocks]
+    double2 *comp;         // its per-component nodes, written by the finish blocks
+    uint32_t fin_nblocks;
+    uint32_t fin;          // 1: the grid's last n blocks reduce the previous pass
     uint32_t N;
     uint32_t first[17];    // first block of component k; first[n] = grid
     uint32_t logR[16];     // strand length R_k = 2^logR[k]
@@ -316,21 +373,27 @@ struct Perm {
 // a j + b - w N in that run, j = c R + s_w + t (t < R) and
 // x = c a R + r_w + a t, where s_w = ceil((w N - b) / a) and
 // r_w = a s_w + b - w N lies in [0, a).
-template <int NC>
+template <class Nd, int NC>
 __global__ __launch_bounds__(kThreads) void k_stream_permute(Perm P)
 {
     extern __shared__ __attribute__((aligned(16))) float run[];
     __shared__ int32_t s_tab[kMaxStrands];
     __shared__ int32_t r_tab[kMaxStrands];
-    const GenState st = *P.state;
-    if (st.flags & WALLACE_FLAG_CORRUPT) return;
+    if (P.fin && blockIdx.x >= P.first[NC]) {
+        // previous pass, component k: its node for the next pass kernel
+        const uint32_t k = blockIdx.x - P.first[NC];
+        const Nd r = comp_sum<Nd, kThreads>(P.partials + (size_t)k * P.fin_nblocks, P.fin_nblocks);
+        if (threadIdx.x == 0) P.comp[k] = r.pack();
+        return;
+    }
+    if (P.state->flags & WALLACE_FLAG_CORRUPT) return;
     const uint32_t N = P.N;
     int k = 0;
 #pragma unroll
     for (int q = 1; q < NC; ++q) k += blockIdx.x >= P.first[q] ? 1 : 0;
     const uint32_t c = blockIdx.x - P.first[k];
     // draw k + 1 of the pass (the same draw the combine kernel makes)
-    uint64_t rng = st.rng + (uint64_t)k * 0x9E3779B97F4A7C15ull;
+    uint64_t rng = P.rng + (uint64_t)k * 0x9E3779B97F4A7C15ull;
     const uint64_t w64 = sm64(rng);
     const uint32_t a = stride_of(k, (uint32_t)(w64 >> 63)) & (N - 1u);
     const uint32_t b = (uint32_t)w64 & (N - 1u);
@@ -344,8 +407,11 @@ __global__ __launch_bounds__(kThreads) void k_stream_permute(Perm P)
     for (uint32_t i = threadIdx.x * 4u; i < len; i += kThreads * 4u)
         *reinterpret_cast<v4f *>(run + i) = *reinterpret_cast<const v4f *>(src + i);
     for (uint32_t w = threadIdx.x; w <= a; w += kThreads) {
+        // ceil(num / a) through one correctly rounded FP64 division: |num| <
+        // 2^32, and a non-integral quotient lies at least 1/a from an
+        // integer, far above its rounding error
         const int64_t num = (int64_t)w * (int64_t)N - (int64_t)b;
-        const int64_t q = num >= 0 ? (num + (int64_t)a - 1) / (int64_t)a : -((-num) / (int64_t)a);
+        const int64_t q = (int64_t)__builtin_ceil((double)num / (double)a);
         s_tab[w] = (int32_t)q;
         r_tab[w] = (int32_t)(q * (int64_t)a - num);
     }
@@ -438,7 +504,7 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
     const uint32_t mask = N - 1u;
     const uint32_t nu = NC * N;
 
-    uint64_t rng = st.rng;
+    uint64_t rng = P.rng;
     uint32_t a[NC], b[NC], signs = 0;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -449,14 +515,28 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
         b[k] = (uint32_t)w & mask;
         if (NC == 16) signs |= (uint32_t)((w >> 62) & 1u) << k;
     }
-    const int mat = (NC == 4) ? (int)(st.passes & 1u) : 0;
+    const int mat = (NC == 4) ? (int)P.mat : 0;
 
     // chi-squared scale from the old pool (section 4, eq. 3)
     const double xstar = (double)P.X[nu - 1];
     const double t = xstar + P.r_nu;
     const double S = (t * t) * 0.5;
-    const float c32 = (float)__builtin_sqrt(S / st.sigma);
+    double sigma_old = st.sigma;
+    if (P.comp) {  // the previous pass of this call, from its component nodes
+        Nd t[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) t[k] = Nd::unpack(P.comp[k]);
+#pragma unroll
+        for (int w = NC; w > 1; w >>= 1) {
+#pragma unroll
+            for (int i = 0; i < w / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
+        }
+        sigma_old = t[0].value();
+    }
+    const float c32 = (float)__builtin_sqrt(S / sigma_old);
     const float h = c32 * (NC == 4 ? 0.5f : 0.25f);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !__builtin_isfinite(c32))
+        atomicOr(&P.state->flags, (uint32_t)WALLACE_FLAG_NONFINITE);
 
     const uint32_t j0 = (blockIdx.x * kThreads + threadIdx.x) * (uint32_t)T;
     float X[NC][T];
@@ -539,29 +619,22 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
     block_partials<Nd, NC, T>(X, P.partials, P.nblocks, red);
 }
 
-// Finish of a pass (one block, after the pass kernel): the sum of squares
-// of the new pool from the per-block partials, and the generator state for
-// the next pass. A separate launch, so no block of the pass kernel needs a
-// device-wide fence (each would write back the whole L2).
+// Finish of a call's last pass (one block, after the pass kernel), and of
+// every pass of the gather form. A launch of its own: no block of the pass
+// kernel needs a device-wide fence (each would write back the whole L2).
 template <class Nd, int NC>
-__global__ __launch_bounds__(kFinThreads) void k_stream_finish(Pass P)
+__global__ __launch_bounds__(kThreads) void k_stream_finish(Pass P)
 {
-    const GenState st = *P.state;
-    if (st.flags & WALLACE_FLAG_CORRUPT) return;
-    const uint32_t nu = NC * P.N;
-    const double xstar = (double)P.X[nu - 1];
-    const double t = xstar + P.r_nu;
-    const double S = (t * t) * 0.5;
-    const float c32 = (float)__builtin_sqrt(S / st.sigma);
-    const double sigma = final_tree<Nd, NC>(P.partials, P.nblocks);
-    if (threadIdx.x == 0) {
-        GenState ns = st;
-        ns.rng = st.rng + (uint64_t)NC * 0x9E3779B97F4A7C15ull;
-        ns.sigma = sigma;
-        ns.passes = st.passes + 1;
-        if (!__builtin_isfinite(c32)) ns.flags |= WALLACE_FLAG_NONFINITE;
-        *P.state = ns;
-    }
+    finish_pass<Nd, NC, kThreads>(P.state, P.partials, P.nblocks, P.passes,
+                                  P.rng + (uint64_t)NC * 0x9E3779B97F4A7C15ull);
+}
+
+template <int NC>
+const void *permute_fn(uint32_t rmode)
+{
+    if (rmode == 1) return reinterpret_cast<const void *>(&k_stream_permute<F32, NC>);
+    if (rmode == 2) return reinterpret_cast<const void *>(&k_stream_permute<F32C, NC>);
+    return reinterpret_cast<const void *>(&k_stream_permute<F64, NC>);
 }
 
 template <int NC>
@@ -630,7 +703,7 @@ uint32_t stride_lo(int k)
 }
 
 // Launch shape of the permute kernel: R_k the largest power of two with
-// hi_k R_k <= kRunFloats; enough blocks for the smaller stride of the pair.
+// hi_k R_k <= run_floats(n); enough blocks for the smaller stride of the pair.
 Perm perm_shape(int n, uint32_t N)
 {
     Perm p{};
@@ -638,7 +711,7 @@ Perm perm_shape(int n, uint32_t N)
     uint32_t blocks = 0;
     for (int k = 0; k < n; ++k) {
         uint32_t logR = 2;
-        while ((stride_hi(k) << (logR + 1)) <= kRunFloats) ++logR;
+        while ((stride_hi(k) << (logR + 1)) <= run_floats(n)) ++logR;
         p.logR[k] = logR;
         p.first[k] = blocks;
         const uint64_t run = (uint64_t)stride_lo(k) << logR;
@@ -669,7 +742,7 @@ size_t stream_partials_bytes(int n, uint32_t N)
 {
     if (!stream_shape_ok(n, N, 0)) return 0;
     const uint32_t nb = N / (kThreads * (uint32_t)stream_T(n, N));
-    return (size_t)n * nb * sizeof(double2);
+    return ((size_t)n * nb + (size_t)n) * sizeof(double2);  // partials, component nodes
 }
 
 const float *stream_current_pool(wallace_gen *g)
@@ -689,7 +762,7 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
                       uint32_t affine, float mu, float sig, hipStream_t s)
 {
     // prime-pair strides keep a * R small enough for the LDS runs
-    const bool perm = g->opts.a_mode == 0 && g->N >= kRunFloats;
+    const bool perm = g->opts.a_mode == 0 && g->N >= kRunFloatsMax;
     const void *fn = pass_kernel(g->n, g->N, (uint32_t)g->opts.reduce_mode, perm,
                                  g->opts.transform_mode == 1);
     if (!fn) return hipErrorInvalidValue;
@@ -701,9 +774,10 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
     if (perm) {
         pm = perm_shape(g->n, g->N);
         pm_lds = perm_lds_bytes(pm, g->n);
-        pfn = g->n == 4 ? reinterpret_cast<const void *>(&k_stream_permute<4>)
-                        : reinterpret_cast<const void *>(&k_stream_permute<16>);
+        pfn = g->n == 4 ? permute_fn<4>((uint32_t)g->opts.reduce_mode)
+                        : permute_fn<16>((uint32_t)g->opts.reduce_mode);
         pm.state = g->state;
+        pm.partials = reinterpret_cast<const double2 *>(g->ws + g->lay.partials);
     }
     const int T = stream_T(g->n, g->N);
     const uint32_t nblocks = g->N / (kThreads * (uint32_t)T);
@@ -743,17 +817,30 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
         P.N = g->N;
         P.a_mode = (uint32_t)g->opts.a_mode;
         P.nblocks = nblocks;
+        const uint64_t q = g->passes_host + ps;  // passes since init
+        P.rng = g->rng0 + (uint64_t)g->n * q * 0x9E3779B97F4A7C15ull;
+        P.mat = (uint32_t)(q & 1u);
+        P.passes = q + 1;
+        double2 *comp = reinterpret_cast<double2 *>(g->ws + g->lay.partials) +
+                        (size_t)g->n * nblocks;
+        P.comp = nullptr;
         if (perm) {
             pm.X = P.X;
             pm.G = P.Y;
+            pm.rng = P.rng;
+            pm.fin = ps > 0 ? 1u : 0u;  // this call's previous pass
+            pm.fin_nblocks = nblocks;
+            pm.comp = comp;
+            if (pm.fin) P.comp = comp;
             void *pargs[] = {&pm};
-            hipError_t e = hipLaunchKernel(pfn, dim3(pm.first[g->n]), dim3(kThreads), pargs,
-                                           pm_lds, s);
+            hipError_t e = hipLaunchKernel(pfn, dim3(pm.first[g->n] + pm.fin * (uint32_t)g->n),
+                                           dim3(kThreads), pargs, pm_lds, s);
             if (e != hipSuccess) return e;
         }
         void *args[] = {&P};
         hipError_t e = hipLaunchKernel(fn, dim3(nblocks), dim3(kThreads), args, 0, s);
-        if (e == hipSuccess) e = hipLaunchKernel(ffn, dim3(1), dim3(kFinThreads), args, 0, s);
+        if (e == hipSuccess && (!perm || ps + 1 == passes))
+            e = hipLaunchKernel(ffn, dim3(1), dim3(kThreads), args, 0, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

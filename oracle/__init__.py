@@ -61,6 +61,17 @@ def lib():
     L.wo_pass_params.restype = None
     L.wo_pass_params.argtypes = [_u64p, ctypes.c_int, ctypes.c_uint32,
                                  ctypes.c_int, _u32p, _u32p, _u32p]
+    L.wo_pass_params_rot.restype = None
+    L.wo_pass_params_rot.argtypes = [_u64p, ctypes.c_int, ctypes.c_uint32,
+                                     ctypes.c_int, _u32p, _u32p, _u32p, _f64p]
+    L.wo_rotation.restype = None
+    L.wo_rotation.argtypes = [ctypes.c_uint64, _f64p, _f64p]
+    L.wo_pass32_rot.restype = None
+    L.wo_pass32_rot.argtypes = [ctypes.c_uint32, _u32p, _u32p, ctypes.c_float,
+                                ctypes.c_float, _f32p, _f32p]
+    L.wo_pass64_rot.restype = None
+    L.wo_pass64_rot.argtypes = [ctypes.c_uint32, _u32p, _u32p, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, _f64p, _f64p]
     for name, rt, pt in (("wo_sumsq_f64", ctypes.c_double, _f32p),
                          ("wo_sumsq_f32", ctypes.c_float, _f32p),
                          ("wo_sumsq_f32c", ctypes.c_double, _f32p),
@@ -148,6 +159,46 @@ def pass_params(state: int, n: int, N: int, a_mode: int = A_PAIRS):
     lib().wo_pass_params(ctypes.byref(s), n, N, a_mode, _ptr(a, _u32p),
                          _ptr(b, _u32p), ctypes.byref(signs))
     return a, b, signs.value, s.value
+
+
+def pass_params_rot(state: int, n: int, N: int, a_mode: int = A_PAIRS):
+    """Return (a, b, signs, (cos, sin), new_state); the rotation is NaN for n != 2."""
+    s = ctypes.c_uint64(state)
+    a = np.empty(n, dtype=np.uint32)
+    b = np.empty(n, dtype=np.uint32)
+    signs = ctypes.c_uint32()
+    rot = np.full(2, np.nan)
+    lib().wo_pass_params_rot(ctypes.byref(s), n, N, a_mode, _ptr(a, _u32p),
+                             _ptr(b, _u32p), ctypes.byref(signs), _ptr(rot, _f64p))
+    return a, b, signs.value, (float(rot[0]), float(rot[1])), s.value
+
+
+def rotation(w: int):
+    """(cos theta, sin theta) of an n = 2 pass from its draw w (section 8)."""
+    cs = ctypes.c_double()
+    sn = ctypes.c_double()
+    lib().wo_rotation(w, ctypes.byref(cs), ctypes.byref(sn))
+    return cs.value, sn.value
+
+
+def pass32_rot(N, a, b, p, q, X):
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    b = np.ascontiguousarray(b, dtype=np.uint32)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.empty_like(X)
+    lib().wo_pass32_rot(N, _ptr(a, _u32p), _ptr(b, _u32p), float(p), float(q),
+                        _ptr(X, _f32p), _ptr(Y, _f32p))
+    return Y
+
+
+def pass64_rot(N, a, b, cs, sn, c, X):
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    b = np.ascontiguousarray(b, dtype=np.uint32)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.empty_like(X)
+    lib().wo_pass64_rot(N, _ptr(a, _u32p), _ptr(b, _u32p), float(cs), float(sn), float(c),
+                        _ptr(X, _f64p), _ptr(Y, _f64p))
+    return Y
 
 
 def sumsq_f64(y: np.ndarray) -> float:

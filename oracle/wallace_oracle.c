@@ -14,6 +14,8 @@
  *   - strides: per component k a pair of primes, one picked per pass by the
  *     top bit of a draw; k = 0, 1 are RANN4's {3,5} and {7,11} (section 8);
  *     offsets uniform on {0..N-1} (section 8);
+ *   - n = 2 (RANN4, section 8): a rotation by theta drawn each pass, with
+ *     sin and cos from t = tan(theta/2) (see wo_rotation);
  *   - matrices: n = 4 alternates A0 = H4/2 and A1 = J/2 - I (section 3 says
  *     Wallace picks among two predefined 4x4 matrices); n = 16 uses H16 D/4
  *     with D a diagonal of random signs drawn each pass (section 3 asks for a
@@ -100,6 +102,39 @@ void wo_initial_pool64(uint64_t *state, int n, uint32_t N, double *pool)
 void wo_pass_params(uint64_t *state, int n, uint32_t N, int a_mode,
                     uint32_t *a, uint32_t *b, uint32_t *signs)
 {
+    wo_pass_params_rot(state, n, N, a_mode, a, b, signs, NULL);
+}
+
+/* Section 8: RANN4 rotates by theta with min(|sin|, |cos|) >= 1/2, choosing
+ * t = tan(theta/2) with a uniform generator and getting sin and cos from t
+ * by a few arithmetic operations (no trigonometric functions). Readings:
+ * the three theta intervals as printed are equally likely; t is uniform on
+ * the image of the chosen interval; tan(pi/12) = 2 - sqrt 3,
+ * tan(pi/6) = 1/sqrt 3, tan(pi/3) = sqrt 3, tan(5pi/12) = 2 + sqrt 3. */
+void wo_rotation(uint64_t w, double *cs, double *sn)
+{
+    double r3 = sqrt(3.0);
+    double tA = 2.0 - r3, tB = 1.0 / r3, tC = r3, tD = 2.0 + r3;
+    double lo, hi, u, t, t2, den;
+    unsigned i = (unsigned)((w >> 32) % 3u);
+    if (i == 0) {        /* theta in [pi/6, pi/3] */
+        lo = tA; hi = tB;
+    } else if (i == 1) { /* theta in [-pi/3, -pi/6] */
+        lo = -tB; hi = -tA;
+    } else {             /* theta in [2pi/3, 5pi/6] */
+        lo = tC; hi = tD;
+    }
+    u = (double)(w & 0xFFFFFFFFull) * (1.0 / 4294967296.0);
+    t = lo + (hi - lo) * u;
+    t2 = t * t;
+    den = 1.0 + t2;
+    *cs = (1.0 - t2) / den;
+    *sn = (t + t) / den;
+}
+
+void wo_pass_params_rot(uint64_t *state, int n, uint32_t N, int a_mode,
+                        uint32_t *a, uint32_t *b, uint32_t *signs, double *rot)
+{
     int k;
     *signs = 0;
     for (k = 0; k < n; ++k) {
@@ -115,6 +150,12 @@ void wo_pass_params(uint64_t *state, int n, uint32_t N, int a_mode,
         /* n = 16: a fresh column sign per component and pass, so that the
          * matrix differs at each pass (section 3). */
         if (n == 16 && ((w >> 62) & 1u)) *signs |= 1u << k;
+    }
+    if (n == 2) { /* the pass's rotation: one more draw */
+        uint64_t w = wo_splitmix64(state);
+        double cs, sn;
+        wo_rotation(w, &cs, &sn);
+        if (rot) { rot[0] = cs; rot[1] = sn; }
     }
 }
 
@@ -326,6 +367,39 @@ void wo_pass64(int n, uint32_t N, int mat, const uint32_t *a,
     }
 }
 
+void wo_pass32_rot(uint32_t N, const uint32_t *a, const uint32_t *b, float p, float q,
+                   const float *X, float *Y)
+{
+    uint32_t j;
+    for (j = 0; j < N; ++j) {
+        uint64_t ix = ((uint64_t)a[0] * j + b[0]) % N; /* eq. 1 */
+        uint64_t iy = ((uint64_t)a[1] * j + b[1]) % N;
+        float x = X[ix], y = X[(size_t)N + iy];
+        float px = p * x, qy = q * y, py = p * y, qx = q * x;
+        Y[j] = px + qy;
+        Y[(size_t)N + j] = py - qx;
+    }
+}
+
+void wo_pass64_rot(uint32_t N, const uint32_t *a, const uint32_t *b, double cs,
+                   double sn, double c, const double *X, double *Y)
+{
+    double M[4];
+    uint32_t j;
+    int k, i;
+    M[0] = cs; M[1] = sn; M[2] = -sn; M[3] = cs;
+    for (j = 0; j < N; ++j) {
+        double v[2];
+        v[0] = X[((uint64_t)a[0] * j + b[0]) % N];
+        v[1] = X[(size_t)N + ((uint64_t)a[1] * j + b[1]) % N];
+        for (k = 0; k < 2; ++k) {
+            double acc = 0.0;
+            for (i = 0; i < 2; ++i) acc += M[k * 2 + i] * v[i];
+            Y[(size_t)k * N + j] = c * acc;
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Generators                                                                */
 /* ------------------------------------------------------------------------ */
@@ -402,9 +476,30 @@ void wo_gen_destroy(wo_gen *g)
 void wo_gen_pass(wo_gen *g)
 {
     uint32_t a[16], b[16], signs;
+    double rot[2];
     uint64_t p = g->passes + 1;
     int mat = (g->n == 4) ? (int)((p - 1) % 2) : 0;
-    wo_pass_params(&g->rng, g->n, g->N, g->a_mode, a, b, &signs);
+    wo_pass_params_rot(&g->rng, g->n, g->N, g->a_mode, a, b, &signs, rot);
+    if (g->n == 2) {
+        /* section 4: the chi-squared scale folds into the rotation */
+        if (!g->fp64) {
+            float *t;
+            wo_scale32((double)g->X32[g->nu - 1], g->sigma, g->nu, &g->last_S,
+                       &g->last_c64);
+            wo_pass32_rot(g->N, a, b, (float)(g->last_c64 * rot[0]),
+                          (float)(g->last_c64 * rot[1]), g->X32, g->Y32);
+            t = g->X32; g->X32 = g->Y32; g->Y32 = t;
+            g->sigma = wo_sumsq_mode(g->X32, g->nu, g->sum_mode);
+        } else {
+            double *t;
+            wo_scale32(g->X64[g->nu - 1], g->sigma, g->nu, &g->last_S, &g->last_c64);
+            wo_pass64_rot(g->N, a, b, rot[0], rot[1], g->last_c64, g->X64, g->Y64);
+            t = g->X64; g->X64 = g->Y64; g->Y64 = t;
+            g->sigma = wo_sumsq_d(g->X64, g->nu);
+        }
+        g->passes = p;
+        return;
+    }
     if (!g->fp64) {
         float c32 = wo_scale32((double)g->X32[g->nu - 1], g->sigma, g->nu,
                                &g->last_S, &g->last_c64);

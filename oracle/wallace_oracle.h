@@ -49,9 +49,21 @@ void wo_initial_pool64(uint64_t *state, int n, uint32_t N, double *pool);
 /* ---- per-pass parameters (eq. 1, eq. 2, sections 3 and 8) -------------- */
 
 /* One draw per component k = 0..n-1: a[k] (odd stride), b[k] (offset);
- * for n = 16 also bit k of *signs (column sign of the matrix). */
+ * for n = 16 also bit k of *signs (column sign of the matrix). For n = 2
+ * (RANN4, section 8) a third draw gives the rotation; see wo_rotation. */
 void wo_pass_params(uint64_t *state, int n, uint32_t N, int a_mode,
                     uint32_t *a, uint32_t *b, uint32_t *signs);
+/* The same, also returning the n = 2 rotation (rot[0] = cos theta,
+ * rot[1] = sin theta; untouched for other n). */
+void wo_pass_params_rot(uint64_t *state, int n, uint32_t N, int a_mode,
+                        uint32_t *a, uint32_t *b, uint32_t *signs, double *rot);
+
+/* Rotation of an n = 2 pass from one draw w (section 8): theta in one of
+ * [pi/6, pi/3], [-pi/3, -pi/6], [2pi/3, 5pi/6], picked by (w >> 32) mod 3;
+ * t = tan(theta/2) uniform in that interval's image with u = (w mod 2^32)
+ * 2^-32; cos theta = (1 - t^2)/(1 + t^2), sin theta = 2t/(1 + t^2), each
+ * step one FP64 operation. */
+void wo_rotation(uint64_t w, double *cs, double *sn);
 
 /* ---- sum of squares (section 4) ----------------------------------------- */
 
@@ -85,6 +97,15 @@ void wo_pass64(int n, uint32_t N, int mat, const uint32_t *a,
 
 /* Dense n x n matrix used by wo_pass64 (row-major), for tests. */
 void wo_matrix(int n, int mat, double *M);
+
+/* n = 2 passes (RANN4). FP32: with p = RN32(c cos theta), q = RN32(c sin
+ * theta), x'_j = p x + q y and y'_j = p y - q x, each product and the sum
+ * rounded once (two multiplies and one add per number, section 7).
+ * FP64: Y = c [[cs, sn], [-sn, cs]] v. */
+void wo_pass32_rot(uint32_t N, const uint32_t *a, const uint32_t *b, float p, float q,
+                   const float *X, float *Y);
+void wo_pass64_rot(uint32_t N, const uint32_t *a, const uint32_t *b, double cs,
+                   double sn, double c, const double *X, double *Y);
 
 /* ---- generators ------------------------------------------------------------- */
 

@@ -492,3 +492,130 @@ def test_oracle_matches_frozen_stream_heads():
         assert [f"{int(v):08x}" for v in x[-32:].view(np.uint32)] == case["tail_bits"]
         assert float(gen.sigma).hex() == case["sigma_hex"]
         assert str(gen.rng) == case["rng"]
+
+
+# ---------------------------------------------------------------------------
+# n = 2: RANN4's random rotation (section 8)
+# ---------------------------------------------------------------------------
+
+_GAMMA = 0x9E3779B97F4A7C15
+
+
+def _theta_ok(theta):
+    # section 8: pi/6 <= |theta| <= pi/3 or 2pi/3 <= theta <= 5pi/6
+    a = abs(theta)
+    eps = 1e-12
+    return (math.pi / 6 - eps <= a <= math.pi / 3 + eps or
+            2 * math.pi / 3 - eps <= theta <= 5 * math.pi / 6 + eps)
+
+
+def test_rotation_matches_trigonometry_and_ranges():
+    # sin and cos from t = tan(theta/2) by rational formulas must equal the
+    # trigonometric functions of theta = 2 atan(t), lie in the printed
+    # ranges, keep min(|sin|, |cos|) >= 1/2 and hit all three intervals.
+    rng = np.random.default_rng(11)
+    hits = [0, 0, 0]
+    for w in rng.integers(0, 1 << 63, size=3000, dtype=np.uint64):
+        w = int(w) ^ (int(rng.integers(0, 2)) << 63)
+        cs, sn = oracle.rotation(w)
+        i = (w >> 32) % 3
+        hits[i] += 1
+        u = (w & 0xFFFFFFFF) / 2.0 ** 32
+        lo_hi = {0: (math.tan(math.pi / 12), math.tan(math.pi / 6)),
+                 1: (-math.tan(math.pi / 6), -math.tan(math.pi / 12)),
+                 2: (math.tan(math.pi / 3), math.tan(5 * math.pi / 12))}[i]
+        t = lo_hi[0] + (lo_hi[1] - lo_hi[0]) * u
+        theta = 2 * math.atan(t)
+        assert abs(cs - math.cos(theta)) < 1e-14 and abs(sn - math.sin(theta)) < 1e-14
+        assert _theta_ok(math.atan2(sn, cs))
+        assert min(abs(cs), abs(sn)) >= 0.5 - 1e-14
+        assert abs(cs * cs + sn * sn - 1.0) < 1e-15
+    assert min(hits) > 800
+
+
+def test_rotation_interval_endpoints():
+    # u = 0 gives the interval's first end: theta = pi/6, -pi/3, 2pi/3
+    for i, theta in ((0, math.pi / 6), (1, -math.pi / 3), (2, 2 * math.pi / 3)):
+        w = i << 32
+        cs, sn = oracle.rotation(w)
+        assert abs(cs - math.cos(theta)) < 1e-15 and abs(sn - math.sin(theta)) < 1e-15
+
+
+def test_n2_pass_params_are_rann4_sets_plus_one_draw():
+    # alpha in {3,5}, beta in {7,11}, offsets below N, three draws per pass
+    s0 = 99
+    seen = set()
+    s = s0
+    for _ in range(200):
+        a, b, _, rot, s = oracle.pass_params_rot(s, 2, 1024)
+        assert a[0] in (3, 5) and a[1] in (7, 11) and (b < 1024).all()
+        assert min(abs(rot[0]), abs(rot[1])) >= 0.5 - 1e-14
+        seen.add((int(a[0]), int(a[1])))
+    assert seen == {(3, 7), (3, 11), (5, 7), (5, 11)}
+    assert s == (s0 + 3 * 200 * _GAMMA) % (1 << 64)
+
+
+def test_n2_pass32_exact_on_dyadic_inputs():
+    # with dyadic p, q and small dyadic pool values every FP32 product and
+    # sum is exact, so the FP32 pass equals the exact rotation-type map
+    N = 16
+    rng = np.random.default_rng(3)
+    X = (rng.integers(-64, 64, size=2 * N) / 8.0).astype(np.float32)
+    a = np.array([3, 7], np.uint32)
+    b = np.array([5, 2], np.uint32)
+    p, q = np.float32(0.75), np.float32(-0.625)
+    Y = oracle.pass32_rot(N, a, b, p, q, X)
+    for j in range(N):
+        x = Fraction(float(X[(3 * j + 5) % N]))
+        y = Fraction(float(X[N + (7 * j + 2) % N]))
+        assert Fraction(float(Y[j])) == Fraction(0.75) * x + Fraction(-0.625) * y
+        assert Fraction(float(Y[N + j])) == Fraction(0.75) * y - Fraction(-0.625) * x
+
+
+def test_n2_rotation_preserves_sum_of_squares():
+    # unscaled (c = 1): per tuple x'^2 + y'^2 = x^2 + y^2 up to rounding
+    N = 512
+    X = oracle.initial_pool64(5, 2, N)[0].astype(np.float32)
+    a, b, _, (cs, sn), _ = oracle.pass_params_rot(5, 2, N)
+    Y = oracle.pass32_rot(N, a, b, np.float32(cs), np.float32(sn), X)
+    j = np.arange(N)
+    x = X[(a[0].astype(np.int64) * j + b[0]) % N].astype(np.float64)
+    y = X[N + (a[1].astype(np.int64) * j + b[1]) % N].astype(np.float64)
+    before = x * x + y * y
+    after = Y[:N].astype(np.float64) ** 2 + Y[N:].astype(np.float64) ** 2
+    assert np.all(np.abs(after - before) <= 8 * 2.0 ** -24 * before + 1e-30)
+
+
+def test_n2_generator_composes_documented_steps():
+    # params (3 draws) -> c from the old pool -> p = RN32(c cos), q = RN32(c sin)
+    # -> rotation pass -> new sum of squares
+    n, N = 2, 256
+    g = oracle.Gen(31, n, N)
+    X = g.pool
+    sigma = g.sigma
+    s = (31 + n * N * _GAMMA) % (1 << 64)
+    for _ in range(5):
+        a, b, _, (cs, sn), s = oracle.pass_params_rot(s, n, N)
+        _, _, c64 = oracle.scale32(float(X[-1]), sigma, n * N)
+        X = oracle.pass32_rot(N, a, b, np.float32(c64 * cs), np.float32(c64 * sn), X)
+        sigma = oracle.sumsq_f64(X)
+        g.do_pass()
+        assert np.array_equal(g.pool, X) and g.sigma == sigma and g.rng == s
+
+
+def test_n2_fp32_within_1e5_of_fp64_and_dense_matrix():
+    x = oracle.Gen(42, 2, 2048).fill(4096 * 500)
+    y = oracle.Gen64(42, 2, 2048).fill(4096 * 500)
+    e = np.abs(x.astype(np.float64) - y) / np.maximum(1.0, np.abs(y))
+    assert e.max() <= 1e-5
+    # the FP64 pass is the dense product c [[cos, sin], [-sin, cos]] v
+    N = 64
+    X = np.random.default_rng(2).standard_normal(2 * N)
+    a = np.array([5, 11], np.uint32)
+    b = np.array([1, 60], np.uint32)
+    Y = oracle.pass64_rot(N, a, b, 0.6, 0.8, 1.5, X)
+    j = np.arange(N)
+    v0 = X[(5 * j + 1) % N]
+    v1 = X[N + (11 * j + 60) % N]
+    assert np.allclose(Y[:N], 1.5 * (0.6 * v0 + 0.8 * v1), rtol=0, atol=1e-15)
+    assert np.allclose(Y[N:], 1.5 * (-0.8 * v0 + 0.6 * v1), rtol=0, atol=1e-15)

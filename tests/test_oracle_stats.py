@@ -49,7 +49,7 @@ def _chi2_uniform(u, lo, hi, bins=1000):
     return ((counts - e) ** 2 / e).sum()
 
 
-@pytest.mark.parametrize("n,N,passes", [(4, 1024, 1000), (16, 4096, 64)])
+@pytest.mark.parametrize("n,N,passes", [(4, 1024, 1000), (16, 4096, 64), (2, 2048, 1000)])
 def test_moments_and_chi2(n, N, passes):
     x = oracle.Gen(42, n, N).fill(n * N * passes)
     z = _moments_ok(x)

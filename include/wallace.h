@@ -10,9 +10,11 @@
  *     x'_k[j] = c * sum_i A[k][i] x_i[(a_i j + b_i) mod N],   j = 0..N-1,
  *
  * with odd strides a_i and offsets b_i drawn once per pass (eq. 2, sections
- * 3 and 8), an orthogonal n x n matrix A (n = 4: alternately H4/2 and
- * J/2 - I; n = 16: H16 D/4 with random column signs D), and a scale c that
- * gives the new pool a chi-squared sum of squares (section 4, eq. 3).
+ * 3 and 8), an orthogonal n x n matrix A (n = 2: RANN4's rotation by a
+ * random angle theta with min(|sin|, |cos|) >= 1/2, section 8; n = 4:
+ * alternately H4/2 and J/2 - I; n = 16: H16 D/4 with random column signs D),
+ * and a scale c that gives the new pool a chi-squared sum of squares
+ * (section 4, eq. 3).
  * The output stream is the sequence of pools, each in flat order
  * f = k*N + j (section 3).
  *
@@ -94,8 +96,9 @@ const char *wallace_last_error(void);
 
 typedef struct wallace_gen wallace_gen;
 
-/* Workspace bytes needed by one generator with n components (4 or 16) and
- * N tuples (a power of two, N >= n). opts may be NULL.
+/* Workspace bytes needed by one generator with n components (2, 4 or 16)
+ * and N tuples (a power of two, N >= n; n = 2 needs N >= 4). opts may be
+ * NULL.
  * Section 8: the pool occupies about half of the work area in RANN4; here
  * the pool needs 4*n*N bytes, plus a second pool buffer and reduction space
  * when the pool is too large to stay on chip. */

@@ -31,7 +31,7 @@ SOURCES = [("wallace_kernels.hip", [], "wallace_kernels"),
            ("wallace_host.cpp", [], "wallace_host"),
            ("wallace_batch.cpp", [], "wallace_batch"),
            ("wallace_tune.cpp", [], "wallace_tune")]
-for _n in (4, 16):
+for _n in (2, 4, 16):
     for _rm in (0, 1, 2):
         SOURCES.append(("wallace_pool_inst.hip",
                         [f"-DWALLACE_POOL_N={_n}", f"-DWALLACE_POOL_RM={_rm}"],

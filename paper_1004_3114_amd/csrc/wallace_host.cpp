@@ -77,7 +77,7 @@ int ilog2(uint64_t x)
 
 bool shape_ok(int n, uint32_t N)
 {
-    if (n != 4 && n != 16) return false;
+    if (n != 2 && n != 4 && n != 16) return false;
     if (!pow2(N) || N < (uint32_t)n) return false;
     if ((uint64_t)n * N > (1ull << 31)) return false;
     return true;
@@ -89,7 +89,7 @@ bool shape_ok(int n, uint32_t N)
 // fit in 128 KiB of LDS, else half of them per stage.
 bool default_sched(int n, uint32_t N, Sched *out)
 {
-    const int tmax = n == 4 ? 16 : 4;
+    const int tmax = n == 16 ? 4 : 16;
     Sched s{n, 1, 64, n};
     if (N <= 64) {
         s.L = (int)N;
@@ -109,14 +109,14 @@ bool default_sched(int n, uint32_t N, Sched *out)
 }
 
 // One generator alone on the GPU: the pass is a latency chain, so the pool
-// is spread over more lanes (4 tuples per lane for n = 4, 1 for n = 16, up
-// to 1024 lanes) than in a batch, where single-wave groups keep the chip
-// busy with many pools. Measured for n = 4, N = 1024: 2.1 -> 1.06 us per
-// pass.
+// is spread over more lanes (16 values per lane: 8 tuples for n = 2, 4 for
+// n = 4, 1 for n = 16; up to 1024 lanes) than in a batch, where single-wave
+// groups keep the chip busy with many pools. Measured for n = 4, N = 1024:
+// 2.1 -> 1.06 us per pass.
 bool single_sched(int n, uint32_t N, Sched *out)
 {
-    const int tmax = n == 4 ? 16 : 4;
-    Sched s{n, n == 4 ? 4 : 1, 0, n};
+    const int tmax = n == 16 ? 4 : 16;
+    Sched s{n, 16 / n, 0, n};
     if (N < (uint32_t)s.T * (uint32_t)n) s.T = 1;
     while (N / (uint32_t)s.T > 1024) s.T *= 2;
     if (s.T > tmax || N % (uint32_t)s.T) return false;

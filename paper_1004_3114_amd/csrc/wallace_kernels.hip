@@ -167,6 +167,8 @@ __global__ void k_tree_finish(const double2 *root, GenState *state, uint32_t mod
 // ---------------------------------------------------------------------------
 
 namespace pool {
+extern const PoolEntry pool_table_2_0[], pool_table_2_1[], pool_table_2_2[];
+extern const int pool_table_len_2_0, pool_table_len_2_1, pool_table_len_2_2;
 extern const PoolEntry pool_table_4_0[], pool_table_4_1[], pool_table_4_2[];
 extern const PoolEntry pool_table_16_0[], pool_table_16_1[], pool_table_16_2[];
 extern const int pool_table_len_4_0, pool_table_len_4_1, pool_table_len_4_2;
@@ -179,7 +181,10 @@ static const pool::PoolEntry *pool_entry(const Sched &s, uint32_t rm)
     const int nst = s.n / s.C;
     const pool::PoolEntry *tab = nullptr;
     int len = 0;
-    if (s.n == 4) {
+    if (s.n == 2) {
+        tab = rm == 1 ? pool::pool_table_2_1 : rm == 2 ? pool::pool_table_2_2 : pool::pool_table_2_0;
+        len = rm == 1 ? pool::pool_table_len_2_1 : rm == 2 ? pool::pool_table_len_2_2 : pool::pool_table_len_2_0;
+    } else if (s.n == 4) {
         tab = rm == 1 ? pool::pool_table_4_1 : rm == 2 ? pool::pool_table_4_2 : pool::pool_table_4_0;
         len = rm == 1 ? pool::pool_table_len_4_1 : rm == 2 ? pool::pool_table_len_4_2 : pool::pool_table_len_4_0;
     } else if (s.n == 16) {

@@ -87,12 +87,48 @@ __device__ __forceinline__ uint32_t stride_pick(int k, uint32_t top)
 
 // Chi-squared scale (section 4, eq. 3): S = (x* + sqrt(2 nu - 1))^2 / 2,
 // c = sqrt(S / sigma), each step one correctly rounded FP64 operation.
-__device__ __forceinline__ float chi2_scale(double xstar, double sigma, double r_nu)
+__device__ __forceinline__ double chi2_scale64(double xstar, double sigma, double r_nu)
 {
     const double t = xstar + r_nu;
     const double S = (t * t) * 0.5;
     const double q = S / sigma;
-    return (float)__builtin_sqrt(q);
+    return __builtin_sqrt(q);
+}
+
+// Splitmix64 draws per pass: one per component, and for n = 2 one more for
+// the rotation (section 8).
+template <int NC>
+struct Draws {
+    static constexpr int value = NC == 2 ? 3 : NC;
+};
+
+// n = 2 rotation of a pass from its draw w (section 8): theta in one of
+// [pi/6, pi/3], [-pi/3, -pi/6], [2pi/3, 5pi/6] picked by (w >> 32) mod 3,
+// t = tan(theta/2) uniform on that interval's image with u = (w mod 2^32)
+// 2^-32, cos = (1 - t^2)/(1 + t^2), sin = 2t/(1 + t^2), one FP64 operation
+// per step.
+__device__ __forceinline__ void rotation(uint64_t w, double &cs, double &sn)
+{
+    const double r3 = __builtin_sqrt(3.0);
+    const double tA = 2.0 - r3, tB = 1.0 / r3, tC = r3, tD = 2.0 + r3;
+    const uint32_t i = (uint32_t)((w >> 32) % 3u);
+    const double lo = i == 0 ? tA : (i == 1 ? -tB : tC);
+    const double hi = i == 0 ? tB : (i == 1 ? -tA : tD);
+    const double u = (double)(uint32_t)w * (1.0 / 4294967296.0);
+    const double t = lo + (hi - lo) * u;
+    const double t2 = t * t;
+    const double den = 1.0 + t2;
+    cs = (1.0 - t2) / den;
+    sn = (t + t) / den;
+}
+
+// n = 2: x' = p x + q y, y' = p y - q x, each product and the sum rounded
+// once (two multiplies and one add per number, section 7).
+__device__ __forceinline__ void xform2(float (&v)[2], float p, float q)
+{
+    const float px = p * v[0], qy = q * v[1], py = p * v[1], qx = q * v[0];
+    v[0] = px + qy;
+    v[1] = py - qx;
 }
 
 template <bool MW>
@@ -523,7 +559,7 @@ __device__ __forceinline__ uint32_t pass_word(uint64_t rng0, uint32_t pass, int 
                                               uint32_t a_mode, uint32_t *signs)
 {
     constexpr uint32_t mask = (uint32_t)N - 1u;
-    const uint64_t m = (uint64_t)NC * pass + (uint64_t)(k + 1);
+    const uint64_t m = (uint64_t)Draws<NC>::value * pass + (uint64_t)(k + 1);
     const uint64_t w = sm64_mix(rng0 + m * kGamma);
     const uint32_t ak = a_mode ? ((uint32_t)(w >> 32) | 1u) : stride_pick(k, (uint32_t)(w >> 63));
     const uint32_t a = ak & mask, b = (uint32_t)w & mask;
@@ -569,6 +605,7 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
 
     uint32_t words[NC];  // packed (4a, 4b) of pass chunk + qlane, per component
     uint32_t swords = 0; // column signs of that pass (n = 16)
+    double rcs = 0.0, rsn = 0.0;  // rotation of that pass (n = 2)
     uint32_t slot = 0;   // pass index within the chunk
     auto draw_chunk = [&](uint32_t ps0) {
         // this lane's pass of the chunk starting at ps0 (eq. 1, section 8 draws)
@@ -576,6 +613,10 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
 #pragma unroll
         for (int k = 0; k < NC; ++k)
             words[k] = pass_word<NC, N>(rng0, ps0 + qlane, k, P.a_mode, &swords);
+        if constexpr (NC == 2) {
+            const uint64_t m = 3ull * (ps0 + qlane) + 3ull;
+            rotation(sm64_mix(rng0 + m * kGamma), rcs, rsn);
+        }
         slot = 0;
     };
     uint32_t fcount = 0; // passes since the last returned pool
@@ -586,6 +627,13 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
     auto one_pass = [&](uint32_t ps, auto mat_c) {
         constexpr int MAT = decltype(mat_c)::value;
         const uint32_t signs = NC == 16 ? bcast<L>(swords, slot) : 0u;
+        double cs = 0.0, sn = 0.0;
+        if constexpr (NC == 2) {
+            cs = __hiloint2double((int)bcast<L>((uint32_t)__double2hiint(rcs), slot),
+                                  (int)bcast<L>((uint32_t)__double2loint(rcs), slot));
+            sn = __hiloint2double((int)bcast<L>((uint32_t)__double2hiint(rsn), slot),
+                                  (int)bcast<L>((uint32_t)__double2loint(rsn), slot));
+        }
         double xstar = 0.0;
 #pragma unroll
         for (int st = 0; st < NST; ++st) {
@@ -624,9 +672,14 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
         }
         ++slot;
 
-        const float c32 = chi2_scale(xstar, sigma, P.r_nu);
+        const double c64 = chi2_scale64(xstar, sigma, P.r_nu);
+        const float c32 = (float)c64;
         if (!__builtin_isfinite(c32)) flags |= WALLACE_FLAG_NONFINITE;
+        // n = 4, 16: the matrix's power-of-two factor; n = 2: c folds into
+        // the rotation entries, each rounded once (section 4)
         const float h = c32 * (NC == 4 ? 0.5f : 0.25f);
+        const float rp = NC == 2 ? (float)(c64 * cs) : 0.0f;
+        const float rq = NC == 2 ? (float)(c64 * sn) : 0.0f;
 #pragma unroll
         for (int i = 0; i < T; ++i) {
             float v[NC];
@@ -634,6 +687,8 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
             for (int k = 0; k < NC; ++k) v[k] = X[k][i];
             if constexpr (NC == 4)
                 xform4(v, MAT, h);
+            else if constexpr (NC == 2)
+                xform2(v, rp, rq);
             else
                 xform16(v, signs, h);
 #pragma unroll
@@ -682,7 +737,7 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
 #pragma unroll
     for (int k = 0; k < NC; ++k) store_run<T>(wpool + k * N + T * lane, X[k], false);
     if (lane == 0) {
-        stp->rng = rng0 + (uint64_t)NC * passes * kGamma;
+        stp->rng = rng0 + (uint64_t)Draws<NC>::value * passes * kGamma;
         stp->sigma = sigma;
         stp->passes = done + passes;
         stp->flags = flags;
@@ -721,6 +776,18 @@ __global__ __launch_bounds__((L > 64 ? L : 256)) void k_pool(PoolArgs P)
     X(4, 4, 128, 1) X(4, 4, 256, 1) X(4, 4, 512, 1) X(4, 4, 1024, 1)                     \
     X(4, 8, 128, 1) X(4, 8, 256, 1) X(4, 8, 512, 1) X(4, 8, 1024, 1)                     \
     X(4, 16, 128, 1) X(4, 16, 256, 1) X(4, 16, 512, 1) X(4, 16, 1024, 2)
+
+#define WALLACE_POOL_SHAPES_2(X)                                                         \
+    X(2, 1, 4, 1) X(2, 1, 8, 1) X(2, 1, 16, 1) X(2, 1, 32, 1) X(2, 1, 64, 1)             \
+    X(2, 2, 4, 1) X(2, 2, 8, 1) X(2, 2, 16, 1) X(2, 2, 32, 1) X(2, 2, 64, 1)             \
+    X(2, 4, 4, 1) X(2, 4, 8, 1) X(2, 4, 16, 1) X(2, 4, 32, 1) X(2, 4, 64, 1)             \
+    X(2, 8, 4, 1) X(2, 8, 8, 1) X(2, 8, 16, 1) X(2, 8, 32, 1) X(2, 8, 64, 1)             \
+    X(2, 16, 4, 1) X(2, 16, 8, 1) X(2, 16, 16, 1) X(2, 16, 32, 1) X(2, 16, 64, 1)        \
+    X(2, 1, 128, 1) X(2, 1, 256, 1) X(2, 1, 512, 1) X(2, 1, 1024, 1)                     \
+    X(2, 2, 128, 1) X(2, 2, 256, 1) X(2, 2, 512, 1) X(2, 2, 1024, 1)                     \
+    X(2, 4, 128, 1) X(2, 4, 256, 1) X(2, 4, 512, 1) X(2, 4, 1024, 1)                     \
+    X(2, 8, 128, 1) X(2, 8, 256, 1) X(2, 8, 512, 1) X(2, 8, 1024, 1)                     \
+    X(2, 16, 128, 1) X(2, 16, 256, 1) X(2, 16, 512, 1) X(2, 16, 1024, 1)
 
 #define WALLACE_POOL_SHAPES_16(X)                                                        \
     X(16, 1, 16, 1) X(16, 1, 32, 1) X(16, 1, 64, 1)                                      \

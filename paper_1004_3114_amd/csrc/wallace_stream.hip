@@ -32,6 +32,26 @@ __device__ __forceinline__ uint64_t sm64(uint64_t &s)
     return z ^ (z >> 31);
 }
 
+// n = 2 rotation of a pass from its draw w (section 8): theta in one of
+// [pi/6, pi/3], [-pi/3, -pi/6], [2pi/3, 5pi/6] picked by (w >> 32) mod 3,
+// t = tan(theta/2) uniform on that interval's image with u = (w mod 2^32)
+// 2^-32, cos = (1 - t^2)/(1 + t^2), sin = 2t/(1 + t^2), one FP64 operation
+// per step.
+__device__ __forceinline__ void rotation(uint64_t w, double &cs, double &sn)
+{
+    const double r3 = __builtin_sqrt(3.0);
+    const double tA = 2.0 - r3, tB = 1.0 / r3, tC = r3, tD = 2.0 + r3;
+    const uint32_t i = (uint32_t)((w >> 32) % 3u);
+    const double lo = i == 0 ? tA : (i == 1 ? -tB : tC);
+    const double hi = i == 0 ? tB : (i == 1 ? -tA : tD);
+    const double u = (double)(uint32_t)w * (1.0 / 4294967296.0);
+    const double t = lo + (hi - lo) * u;
+    const double t2 = t * t;
+    const double den = 1.0 + t2;
+    cs = (1.0 - t2) / den;
+    sn = (t + t) / den;
+}
+
 // Component k's stride pair (section 8: {3,5}, {7,11}, then further odd
 // primes so that the strides of different components differ).
 __device__ __forceinline__ uint32_t stride_of(int k, uint32_t top)
@@ -351,7 +371,11 @@ __device__ Nd comp_sum(const double2 *p, uint32_t nblocks)
 // of 4096 values (16 KB) gave n = 4 the most blocks in flight; n = 16, with
 // strides up to 137, needs 8192 to keep its strands at 64 values or more.
 constexpr uint32_t kRunFloatsMax = 8192;
-__host__ __device__ constexpr uint32_t run_floats(int n) { return n == 4 ? 4096u : 8192u; }
+__host__ __device__ constexpr uint32_t run_floats(int n) { return n == 16 ? 8192u : 4096u; }
+
+// Splitmix64 draws per pass: one per component, one more for the n = 2
+// rotation (section 8).
+__host__ __device__ constexpr uint32_t draws_per_pass(int n) { return n == 2 ? 3u : (uint32_t)n; }
 constexpr int kMaxStrands = 160;  // a + 1 for the largest prime-pair stride
 
 struct Perm {
@@ -515,6 +539,8 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
         b[k] = (uint32_t)w & mask;
         if (NC == 16) signs |= (uint32_t)((w >> 62) & 1u) << k;
     }
+    double rcs = 0.0, rsn = 0.0;  // n = 2: the pass's rotation (draw n + 1)
+    if constexpr (NC == 2) rotation(sm64(rng), rcs, rsn);
     const int mat = (NC == 4) ? (int)P.mat : 0;
 
     // chi-squared scale from the old pool (section 4, eq. 3)
@@ -533,8 +559,12 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
         }
         sigma_old = t[0].value();
     }
-    const float c32 = (float)__builtin_sqrt(S / sigma_old);
+    const double c64 = __builtin_sqrt(S / sigma_old);
+    const float c32 = (float)c64;
     const float h = c32 * (NC == 4 ? 0.5f : 0.25f);
+    // n = 2: c folds into the rotation entries, each rounded once (section 4)
+    const float rp = NC == 2 ? (float)(c64 * rcs) : 0.0f;
+    const float rq = NC == 2 ? (float)(c64 * rsn) : 0.0f;
     if (blockIdx.x == 0 && threadIdx.x == 0 && !__builtin_isfinite(c32))
         atomicOr(&P.state->flags, (uint32_t)WALLACE_FLAG_NONFINITE);
 
@@ -563,7 +593,11 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
         }
 #pragma unroll
         for (int k = 0; k < NC; ++k) v[k] = ((signs >> k) & 1u) ? -X[k][i] : X[k][i];
-        if constexpr (NC == 4) {
+        if constexpr (NC == 2) {
+            const float px = rp * v[0], qy = rq * v[1], py = rp * v[1], qx = rq * v[0];
+            v[0] = px + qy;
+            v[1] = py - qx;
+        } else if constexpr (NC == 4) {
             const float v0 = mat ? -v[0] : v[0];
             const float s0 = v0 + v[1], s1 = v0 - v[1];
             const float s2 = v[2] + v[3], s3 = v[2] - v[3];
@@ -626,7 +660,7 @@ template <class Nd, int NC>
 __global__ __launch_bounds__(kThreads) void k_stream_finish(Pass P)
 {
     finish_pass<Nd, NC, kThreads>(P.state, P.partials, P.nblocks, P.passes,
-                                  P.rng + (uint64_t)NC * 0x9E3779B97F4A7C15ull);
+                                  P.rng + (uint64_t)draws_per_pass(NC) * 0x9E3779B97F4A7C15ull);
 }
 
 template <int NC>
@@ -666,7 +700,7 @@ const void *pass_fn_mode(uint32_t rmode, bool perm)
 // 4 partials per thread).
 int stream_T(int n, uint32_t N)
 {
-    uint32_t T = n == 4 ? 4u : 1u;
+    uint32_t T = n == 16 ? 1u : 16u / (uint32_t)n;
     while ((uint64_t)N / ((uint64_t)kThreads * T) > 4096) T *= 2;
     return (int)T;
 }
@@ -675,7 +709,10 @@ const void *pass_kernel(int n, uint32_t N, uint32_t rmode, bool perm, bool mf)
 {
     const int T = stream_T(n, N);
     if (mf) return (n == 16 && T == 1) ? pass_fn_mode<16, 1, true>(rmode, perm) : nullptr;
-    if (n == 4) {
+    if (n == 2) {
+        if (T == 8) return pass_fn_mode<2, 8>(rmode, perm);
+        if (T == 16) return pass_fn_mode<2, 16>(rmode, perm);
+    } else if (n == 4) {
         if (T == 4) return pass_fn_mode<4, 4>(rmode, perm);
         if (T == 8) return pass_fn_mode<4, 8>(rmode, perm);
         if (T == 16) return pass_fn_mode<4, 16>(rmode, perm);
@@ -735,7 +772,7 @@ bool stream_shape_ok(int n, uint32_t N, int transform_mode)
     if (N < (uint32_t)kThreads * 4) return false;
     const int T = stream_T(n, N);
     if (transform_mode == 1) return n == 16 && T == 1;
-    return (n == 4 && T <= 16) || (n == 16 && T <= 4);
+    return (n == 2 && T <= 16) || (n == 4 && T <= 16) || (n == 16 && T <= 4);
 }
 
 size_t stream_partials_bytes(int n, uint32_t N)
@@ -766,7 +803,8 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
     const void *fn = pass_kernel(g->n, g->N, (uint32_t)g->opts.reduce_mode, perm,
                                  g->opts.transform_mode == 1);
     if (!fn) return hipErrorInvalidValue;
-    const void *ffn = g->n == 4 ? finish_fn<4>((uint32_t)g->opts.reduce_mode)
+    const void *ffn = g->n == 2   ? finish_fn<2>((uint32_t)g->opts.reduce_mode)
+                      : g->n == 4 ? finish_fn<4>((uint32_t)g->opts.reduce_mode)
                                 : finish_fn<16>((uint32_t)g->opts.reduce_mode);
     Perm pm{};
     size_t pm_lds = 0;
@@ -774,7 +812,8 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
     if (perm) {
         pm = perm_shape(g->n, g->N);
         pm_lds = perm_lds_bytes(pm, g->n);
-        pfn = g->n == 4 ? permute_fn<4>((uint32_t)g->opts.reduce_mode)
+        pfn = g->n == 2   ? permute_fn<2>((uint32_t)g->opts.reduce_mode)
+              : g->n == 4 ? permute_fn<4>((uint32_t)g->opts.reduce_mode)
                         : permute_fn<16>((uint32_t)g->opts.reduce_mode);
         pm.state = g->state;
         pm.partials = reinterpret_cast<const double2 *>(g->ws + g->lay.partials);
@@ -818,7 +857,7 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
         P.a_mode = (uint32_t)g->opts.a_mode;
         P.nblocks = nblocks;
         const uint64_t q = g->passes_host + ps;  // passes since init
-        P.rng = g->rng0 + (uint64_t)g->n * q * 0x9E3779B97F4A7C15ull;
+        P.rng = g->rng0 + (uint64_t)draws_per_pass(g->n) * q * 0x9E3779B97F4A7C15ull;
         P.mat = (uint32_t)(q & 1u);
         P.passes = q + 1;
         double2 *comp = reinterpret_cast<double2 *>(g->ws + g->lay.partials) +

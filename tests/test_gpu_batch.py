@@ -29,7 +29,7 @@ def test_mixed_small_batch_two_launches():
     _dev()
     rng = np.random.default_rng(1)
     shapes = [(4, 4), (4, 64), (4, 256), (4, 1024), (4, 4096), (4, 16384), (16, 16),
-              (16, 64), (16, 256), (16, 1024), (16, 4096)]
+              (16, 64), (16, 256), (16, 1024), (16, 4096), (2, 256), (2, 8192)]
     G = 40
     pick = rng.integers(0, len(shapes), size=G)
     n = np.array([shapes[i][0] for i in pick], dtype=np.int32)
@@ -65,7 +65,8 @@ def test_mixed_batch_graph_replays():
     # stream and must match the oracle, with eager work between replays.
     _dev()
     rng = np.random.default_rng(5)
-    shapes = [(4, 16), (4, 256), (4, 1024), (4, 4096), (16, 16), (16, 256), (16, 1024)]
+    shapes = [(4, 16), (4, 256), (4, 1024), (4, 4096), (16, 16), (16, 256), (16, 1024),
+              (2, 512)]
     G = 28
     pick = np.arange(G) % len(shapes)
     n = np.array([shapes[i][0] for i in pick], dtype=np.int32)
@@ -99,7 +100,8 @@ def test_mixed_batch_graph_replays():
     assert b.status() == (0, 0)
 
 
-@pytest.mark.parametrize("n,N", [(4, 256), (4, 2048), (16, 64), (16, 1024), (4, 16384)])
+@pytest.mark.parametrize("n,N", [(4, 256), (4, 2048), (16, 64), (16, 1024), (4, 16384),
+                                 (2, 1024)])
 def test_every_schedule_gives_identical_bits(n, N, monkeypatch):
     # Schedules differ in lanes per pool, tuples per lane and components per
     # LDS stage; the tree order of every reduction is the same, so each one
@@ -112,7 +114,7 @@ def test_every_schedule_gives_identical_bits(n, N, monkeypatch):
         L = N // T
         if L < n or L > 1024:
             continue
-        for C in (n, n // 2):
+        for C in ((n,) if n == 2 else (n, n // 2)):  # n = 2: one stage only
             if C * N * 4 > 128 * 1024 or (L <= 64 and C != n):
                 continue
             cands.append((T, L, C))

@@ -64,7 +64,8 @@ def test_single_small_full_run():
     assert_bits_equal(g.pool(), ref_gen.pool, "final pool")
 
 
-SHAPES = [(4, 4), (4, 8), (4, 16), (4, 32), (4, 64), (4, 128), (4, 256), (4, 512),
+SHAPES = [(2, 4), (2, 64), (2, 256), (2, 1024), (2, 4096), (2, 16384),
+          (4, 4), (4, 8), (4, 16), (4, 32), (4, 64), (4, 128), (4, 256), (4, 512),
           (4, 1024), (4, 2048), (4, 4096), (4, 8192), (4, 16384),
           (16, 16), (16, 32), (16, 64), (16, 128), (16, 256), (16, 512), (16, 1024),
           (16, 2048), (16, 4096)]
@@ -82,7 +83,7 @@ def test_pool_resident_shapes(n, N):
     assert_bits_equal(got, ref, f"n={n} N={N}")
 
 
-@pytest.mark.parametrize("n,N", [(4, 256), (16, 64), (4, 4096)])
+@pytest.mark.parametrize("n,N", [(4, 256), (16, 64), (4, 4096), (2, 512)])
 def test_ragged_call_splits(n, N):
     _dev()
     rng = np.random.default_rng(N)
@@ -97,7 +98,7 @@ def test_ragged_call_splits(n, N):
 
 
 @pytest.mark.parametrize("mode", [1, 2])
-@pytest.mark.parametrize("n,N", [(4, 1024), (16, 256), (4, 16384)])
+@pytest.mark.parametrize("n,N", [(4, 1024), (16, 256), (4, 16384), (2, 2048)])
 def test_reduce_modes(mode, n, N):
     _dev()
     print(f"case reduce_mode={mode} n={n} N={N}", flush=True)
@@ -117,10 +118,11 @@ def test_full_odd_strides():
     assert_bits_equal(got, ref, "a_mode 1")
 
 
-@pytest.mark.parametrize("f,withhold", [(2, 0), (3, 1), (1, 1)])
-def test_throwaway_and_withheld_driver(f, withhold):
+@pytest.mark.parametrize("n,f,withhold", [(4, 2, 0), (4, 3, 1), (4, 1, 1), (2, 3, 0)])
+def test_throwaway_and_withheld_driver(n, f, withhold):
+    # RANN4 (n = 2) itself uses f = 3 (section 8)
     _dev()
-    n, N = 4, 256
+    N = 256
     emit = n * N - withhold
     g = W.Generator(21, n, N, f=f, withhold_driver=withhold)
     counts = [emit * 3 + 7, emit - 7, 5]
@@ -160,7 +162,8 @@ def test_corruption_is_detected():
 # streaming (pool in HBM)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,N,passes", [(4, 1 << 15, 6), (16, 1 << 13, 6), (4, 1 << 17, 3)])
+@pytest.mark.parametrize("n,N,passes", [(4, 1 << 15, 6), (16, 1 << 13, 6), (4, 1 << 17, 3),
+                                        (2, 1 << 15, 6), (2, 1 << 18, 3)])
 def test_streaming_small(n, N, passes):
     _dev()
     print(f"case stream n={n} N={N}", flush=True)

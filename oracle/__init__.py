@@ -99,6 +99,8 @@ def lib():
     L.wo_gen64_create.restype = ctypes.c_void_p
     L.wo_gen64_create.argtypes = [ctypes.c_uint64, ctypes.c_int,
                                   ctypes.c_uint32, ctypes.c_int]
+    L.wo_gen_set_restart.restype = None
+    L.wo_gen_set_restart.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
     L.wo_gen_destroy.restype = None
     L.wo_gen_destroy.argtypes = [ctypes.c_void_p]
     L.wo_gen_pass.restype = None
@@ -265,9 +267,10 @@ class Gen:
     fp64 = False
 
     def __init__(self, seed: int, n: int, N: int, sum_mode: int = SUM_F64,
-                 a_mode: int = A_PAIRS, f: int = 1, withhold: int = 0):
+                 a_mode: int = A_PAIRS, f: int = 1, withhold: int = 0, restart: int = 0):
         self.n, self.N, self.nu = n, N, n * N
         self._h = lib().wo_gen_create(seed, n, N, sum_mode, a_mode, f, withhold)
+        lib().wo_gen_set_restart(self._h, restart)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -321,6 +324,7 @@ class Gen64(Gen):
 
     fp64 = True
 
-    def __init__(self, seed: int, n: int, N: int, a_mode: int = A_PAIRS):
+    def __init__(self, seed: int, n: int, N: int, a_mode: int = A_PAIRS, restart: int = 0):
         self.n, self.N, self.nu = n, N, n * N
         self._h = lib().wo_gen64_create(seed, n, N, a_mode)
+        lib().wo_gen_set_restart(self._h, restart)

@@ -409,6 +409,7 @@ struct wo_gen {
     uint32_t N;
     size_t nu;
     uint64_t rng;      /* splitmix64 state */
+    uint64_t restart;  /* refill the pool every `restart` passes (0: never) */
     double sigma;      /* sum of squares of the current pool */
     uint64_t passes;   /* passes done */
     size_t cursor;     /* values of the current output pool already emitted */
@@ -473,11 +474,29 @@ void wo_gen_destroy(wo_gen *g)
     free(g);
 }
 
+/* Section 5: restart after a fixed amount of output by refilling the pool
+ * from the uniform generator with Box-Muller, as at initialisation. The
+ * refilled pool is not output; the next pass transforms it. */
+void wo_gen_set_restart(wo_gen *g, uint64_t passes) { g->restart = passes; }
+
+static void gen_refill(wo_gen *g)
+{
+    size_t i;
+    wo_initial_pool64(&g->rng, g->n, g->N, g->X64);
+    if (g->fp64) {
+        g->sigma = wo_sumsq_d(g->X64, g->nu);
+    } else {
+        for (i = 0; i < g->nu; ++i) g->X32[i] = (float)g->X64[i];
+        g->sigma = wo_sumsq_mode(g->X32, g->nu, g->sum_mode);
+    }
+}
+
 void wo_gen_pass(wo_gen *g)
 {
     uint32_t a[16], b[16], signs;
     double rot[2];
     uint64_t p = g->passes + 1;
+    if (g->restart && g->passes > 0 && g->passes % g->restart == 0) gen_refill(g);
     int mat = (g->n == 4) ? (int)((p - 1) % 2) : 0;
     wo_pass_params_rot(&g->rng, g->n, g->N, g->a_mode, a, b, &signs, rot);
     if (g->n == 2) {

@@ -119,6 +119,10 @@ wo_gen *wo_gen_create(uint64_t seed, int n, uint32_t N, int sum_mode,
 /* FP64 generator (accuracy variant): same draws, unrounded pool, dense
  * FP64 matrices, FP64 sum of squares. */
 wo_gen *wo_gen64_create(uint64_t seed, int n, uint32_t N, int a_mode);
+/* Section 5 restarts: before pass p + 1 with p a positive multiple of
+ * `passes`, refill the pool by Box-Muller from the generator's stream (nu
+ * draws, as at initialisation) and recompute its sum of squares. 0: never. */
+void wo_gen_set_restart(wo_gen *g, uint64_t passes);
 void wo_gen_destroy(wo_gen *g);
 
 /* One pass (eq. 1 plus the section-4 rescaling). */

@@ -619,3 +619,43 @@ def test_n2_fp32_within_1e5_of_fp64_and_dense_matrix():
     v1 = X[N + (11 * j + 60) % N]
     assert np.allclose(Y[:N], 1.5 * (0.6 * v0 + 0.8 * v1), rtol=0, atol=1e-15)
     assert np.allclose(Y[N:], 1.5 * (-0.8 * v0 + 0.6 * v1), rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Restarts (section 5)
+# ---------------------------------------------------------------------------
+
+def test_restart_refills_by_box_muller_from_the_stream():
+    # after R passes the pool is replaced by Box-Muller from the generator's
+    # own stream (nu draws, as at initialisation), its sum of squares is
+    # recomputed, and the next pass transforms the refilled pool
+    n, N, R = 4, 64, 3
+    nu = n * N
+    g = oracle.Gen(123, n, N, restart=R)
+    plain = oracle.Gen(123, n, N)
+    for _ in range(R):
+        g.do_pass()
+        plain.do_pass()
+    assert np.array_equal(g.pool, plain.pool)
+    s = g.rng
+    X64, s2 = oracle.initial_pool64(s, n, N)
+    assert s2 == (s + nu * _GAMMA) % (1 << 64)
+    X = X64.astype(np.float32)
+    sigma = oracle.sumsq_f64(X)
+    a, b, _, s3 = oracle.pass_params(s2, n, N)
+    c32, _, _ = oracle.scale32(float(X[-1]), sigma, nu)
+    Y = oracle.pass32(n, N, R % 2, a, b, np.float32(c32 * np.float32(0.5)), X)
+    g.do_pass()
+    assert np.array_equal(g.pool, Y) and g.rng == s3
+    assert g.sigma == oracle.sumsq_f64(Y)
+
+
+def test_restart_stream_statistics_and_fp64_agreement():
+    x = oracle.Gen(8, 4, 1024, restart=50).fill(4096 * 400)
+    y = oracle.Gen64(8, 4, 1024, restart=50).fill(4096 * 400)
+    e = np.abs(x.astype(np.float64) - y) / np.maximum(1.0, np.abs(y))
+    assert e.max() <= 1e-5
+    M = x.size
+    xd = x.astype(np.float64)
+    assert abs(xd.mean()) * math.sqrt(M) < 5
+    assert abs((xd ** 2).mean() - 1) / math.sqrt(2 / M) < 5

@@ -79,6 +79,13 @@ typedef struct wallace_opts {
                                 start of every call and flag a mismatch
                                 (section 8: a large change means the work area
                                 was overwritten)                               */
+    int32_t restart_passes;  /* R > 0: refill the pool by Box-Muller from the
+                                generator's stream after every R passes
+                                (section 5; R a multiple of f; single
+                                generators only). The refill runs on the GPU
+                                with its FP64 log/sin/cos, so it may differ
+                                from the host's libm in the last bit of a rare
+                                value; 0 = never (default)                     */
 } wallace_opts;
 
 /* Fills *opts with the defaults: f = 1, prime-pair strides, FP64 sum of

@@ -210,7 +210,8 @@ int32_t wallace_batch_init(uint32_t G, const uint64_t *seeds, const int32_t *n,
     wallace_opts o;
     wallace_default_opts(&o);
     if (opts) o = *opts;
-    if (o.f != 1 || o.withhold_driver != 0 || o.transform_mode != 0) return WALLACE_EUNSUP;
+    if (o.f != 1 || o.withhold_driver != 0 || o.transform_mode != 0 || o.restart_passes != 0)
+        return WALLACE_EUNSUP;
     if (o.a_mode < 0 || o.a_mode > 1 || o.reduce_mode < 0 || o.reduce_mode > 2 ||
         o.check_workspace < 0 || o.check_workspace > 1)
         return WALLACE_EINVAL;

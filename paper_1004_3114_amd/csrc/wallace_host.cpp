@@ -138,6 +138,25 @@ hipError_t num_cus(int *cus)
 
 double chi2_root(uint64_t nu) { return std::sqrt((double)(2 * nu - 1)); }
 
+uint64_t pass_rng(const wallace_gen *g, uint64_t q)
+{
+    const uint64_t draws = g->n == 2 ? 3u : (uint64_t)g->n;
+    const uint64_t R = (uint64_t)g->opts.restart_passes;
+    const uint64_t refills = R ? q / R : 0;
+    return g->rng0 + (draws * q + g->nu * refills) * 0x9E3779B97F4A7C15ull;
+}
+
+hipError_t refill_pool(wallace_gen *g, float *pool, uint64_t q, hipStream_t s)
+{
+    const uint64_t r0 = pass_rng(g, q) - g->nu * 0x9E3779B97F4A7C15ull;
+    hipError_t e = launch_refill(pool, g->nu, r0, g->state, s);
+    if (e == hipSuccess)
+        e = launch_sumsq(pool, g->nu, (uint32_t)g->opts.reduce_mode,
+                         reinterpret_cast<double *>(g->ws + g->lay.scratch), nullptr, g->state,
+                         0, s);
+    return e;
+}
+
 }  // namespace wallace
 
 // ---------------------------------------------------------------------------
@@ -179,6 +198,7 @@ bool opts_ok(const wallace_opts &o)
     if (o.transform_mode < 0 || o.transform_mode > 1) return false;
     if (o.withhold_driver < 0 || o.withhold_driver > 1) return false;
     if (o.check_workspace < 0 || o.check_workspace > 1) return false;
+    if (o.restart_passes < 0 || (o.restart_passes % o.f) != 0) return false;
     return true;
 }
 
@@ -329,20 +349,33 @@ static int32_t fill_impl(wallace_gen *g, float *d_out, uint64_t count,
             e = stream_run(g, d_out + k0, (uint32_t)passes, (uint32_t)tail, affine, mu,
                            sig, s);
         } else {
+          // restarts split the passes into segments (multiples of f, since
+          // the interval is); each segment is one launch
+          const uint64_t R = (uint64_t)g->opts.restart_passes;
+          const uint32_t f = (uint32_t)g->opts.f;
+          for (uint64_t done = 0; done < passes && e == hipSuccess;) {
+            const uint64_t q = g->passes_host + done;
+            if (R && q > 0 && q % R == 0) {
+                e = refill_pool(g, g->pool, q, s);
+                if (e != hipSuccess) break;
+            }
+            uint64_t seg = passes - done;
+            if (R) seg = std::min<uint64_t>(seg, R - q % R);
+            const bool last = done + seg == passes;
             PoolArgs a{};
             a.jobs = nullptr;
-            a.one.out_off = k0;
+            a.one.out_off = k0 + (done / f) * len;
             a.one.pool_off = 0;
             a.one.gen = 0;
-            a.one.passes = (uint32_t)passes;
-            a.one.last_emit = (uint32_t)tail;
+            a.one.passes = (uint32_t)seg;
+            a.one.last_emit = last ? (uint32_t)tail : (uint32_t)len;
             a.one.cls = 0;
             a.njobs = 1;
             a.f = (uint32_t)g->opts.f;
             a.emit_len = (uint32_t)len;
             a.a_mode = (uint32_t)g->opts.a_mode;
             a.rmode = (uint32_t)g->opts.reduce_mode;
-            a.sigma_mode = g->opts.check_workspace ? 1u : 0u;
+            a.sigma_mode = (g->opts.check_workspace && done == 0) ? 1u : 0u;
             a.affine = affine;
             a.mu = mu;
             a.sigma_out = sig;
@@ -357,6 +390,8 @@ static int32_t fill_impl(wallace_gen *g, float *d_out, uint64_t count,
             a.C = g->sched.C;
             a.groups_per_block = g->sched.L > 64 ? 1 : 256 / g->sched.L;
             e = launch_pool(g->sched, a, 1, s);
+            done += seg;
+          }
         }
         if (e != hipSuccess) return hip_fail(e, "pass launch");
         g->cursor = tail;

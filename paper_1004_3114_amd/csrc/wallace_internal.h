@@ -92,6 +92,9 @@ size_t pool_lds_bytes(const Sched &s, int N);
 bool pool_sched_supported(const Sched &s, int N);
 hipError_t pool_max_blocks_per_cu(const Sched &s, int N, uint32_t rmode, int *blocks);
 
+// Restart refill of a pool (section 5) from the stream at r0; sets state->rng.
+hipError_t launch_refill(float *pool, uint64_t nu, uint64_t r0, GenState *state,
+                         hipStream_t stream);
 hipError_t launch_copy_head(float *out, const float *pool, uint32_t count,
                             uint32_t affine, float mu, float sig,
                             hipStream_t stream);

@@ -98,6 +98,36 @@ __global__ void k_copy_head(float *out, const float *pool, uint32_t count,
     }
 }
 
+// Restart (section 5): refills a pool of nu values by Box-Muller from the
+// splitmix64 stream at state r0, as the initial pool is made: pair m takes
+// draws 2m+1 and 2m+2, u1 = ((w >> 11) + 1) 2^-53 in (0, 1], u2 = (w >> 11)
+// 2^-53, cos to flat index 2m and sin to 2m+1, in FP64 rounded to FP32.
+// The device's FP64 log, cos and sin are not the host's libm, so a value
+// can differ from the host's in its last bit. Writes the state after the nu
+// draws; the sum of squares is recomputed by the tree kernels afterwards.
+__global__ void k_refill(float *pool, uint64_t nu, uint64_t r0, GenState *state)
+{
+    constexpr uint64_t gam = 0x9E3779B97F4A7C15ull;
+    const uint64_t pairs = nu / 2;
+    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < pairs;
+         m += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t z1 = r0 + (2 * m + 1) * gam, z2 = r0 + (2 * m + 2) * gam;
+        z1 = (z1 ^ (z1 >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z1 = (z1 ^ (z1 >> 27)) * 0x94D049BB133111EBull;
+        z1 ^= z1 >> 31;
+        z2 = (z2 ^ (z2 >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z2 = (z2 ^ (z2 >> 27)) * 0x94D049BB133111EBull;
+        z2 ^= z2 >> 31;
+        const double u1 = (double)((z1 >> 11) + 1) * 0x1.0p-53;
+        const double u2 = (double)(z2 >> 11) * 0x1.0p-53;
+        const double rho = __builtin_sqrt(-2.0 * log(u1));
+        const double theta = (2.0 * 3.14159265358979323846) * u2;
+        pool[2 * m] = (float)(rho * cos(theta));
+        pool[2 * m + 1] = (float)(rho * sin(theta));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) state->rng = r0 + nu * gam;
+}
+
 // Copies one generator's state and pool into `copies` slots (tuning runs).
 __global__ void k_replicate(GenState *states, float *pools, uint64_t stride,
                             uint32_t copies, const GenState *src_state,
@@ -242,6 +272,16 @@ hipError_t launch_pool(const Sched &s, const PoolArgs &a, int grid, hipStream_t 
     PoolArgs args = a;
     void *kargs[] = {&args};
     return hipLaunchKernel(e->fn, dim3(grid), dim3(e->block), kargs, (size_t)e->lds_bytes, stream);
+}
+
+hipError_t launch_refill(float *pool, uint64_t nu, uint64_t r0, GenState *state,
+                         hipStream_t stream)
+{
+    uint64_t grid = (nu / 2 + 255) / 256;
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(k_refill, dim3((unsigned)grid), dim3(256), 0, stream, pool, nu, r0,
+                       state);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy_head(float *out, const float *pool, uint32_t count,

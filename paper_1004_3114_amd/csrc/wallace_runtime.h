@@ -54,6 +54,16 @@ struct wallace_gen {
 
 namespace wallace {
 
+// Splitmix64 state before pass q + 1 of a single generator (q passes done
+// since init): the pass draws (n per pass, 3 for n = 2) plus nu per restart
+// refill, which happens before pass q + 1 when q is a positive multiple of
+// the restart interval (section 5).
+uint64_t pass_rng(const wallace_gen *g, uint64_t q);
+
+// Restart refill before pass q + 1 (q a positive multiple of the interval):
+// Box-Muller into `pool`, new state rng and sum of squares.
+hipError_t refill_pool(wallace_gen *g, float *pool, uint64_t q, hipStream_t s);
+
 // Streaming path for pools too large to stay on chip (wallace_stream.hip).
 size_t stream_partials_bytes(int n, uint32_t N);
 bool stream_shape_ok(int n, uint32_t N, int transform_mode);

@@ -828,8 +828,22 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
     // output (one 4 nu-byte stream less). The call's last pass always writes
     // the workspace pool that the next call starts from.
     const float *src = ((g->passes_host & 1) != 0) ? pb : pa;
+    const uint64_t R = (uint64_t)g->opts.restart_passes;
     for (uint32_t ps = 0; ps < passes; ++ps) {
         float *ws_dst = ((g->passes_host + ps + 1) & 1) != 0 ? pb : pa;
+        // restart (section 5): refill into the workspace buffer of this
+        // pass's parity; the pass then starts from the state's new sum
+        bool refilled = false;
+        {
+            const uint64_t q = g->passes_host + ps;
+            if (R && q > 0 && q % R == 0) {
+                float *w = (q & 1) != 0 ? pb : pa;
+                hipError_t e = refill_pool(g, w, q, s);
+                if (e != hipSuccess) return e;
+                src = w;
+                refilled = true;
+            }
+        }
         Pass P{};
         P.X = src;
         P.Y = ws_dst;
@@ -857,7 +871,7 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
         P.a_mode = (uint32_t)g->opts.a_mode;
         P.nblocks = nblocks;
         const uint64_t q = g->passes_host + ps;  // passes since init
-        P.rng = g->rng0 + (uint64_t)draws_per_pass(g->n) * q * 0x9E3779B97F4A7C15ull;
+        P.rng = pass_rng(g, q);
         P.mat = (uint32_t)(q & 1u);
         P.passes = q + 1;
         double2 *comp = reinterpret_cast<double2 *>(g->ws + g->lay.partials) +
@@ -867,7 +881,7 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
             pm.X = P.X;
             pm.G = P.Y;
             pm.rng = P.rng;
-            pm.fin = ps > 0 ? 1u : 0u;  // this call's previous pass
+            pm.fin = (ps > 0 && !refilled) ? 1u : 0u;  // this call's previous pass
             pm.fin_nblocks = nblocks;
             pm.comp = comp;
             if (pm.fin) P.comp = comp;

@@ -42,7 +42,8 @@ class WallaceError(RuntimeError):
 class wallace_opts(ctypes.Structure):
     _fields_ = [("f", ctypes.c_int32), ("a_mode", ctypes.c_int32),
                 ("reduce_mode", ctypes.c_int32), ("transform_mode", ctypes.c_int32),
-                ("withhold_driver", ctypes.c_int32), ("check_workspace", ctypes.c_int32)]
+                ("withhold_driver", ctypes.c_int32), ("check_workspace", ctypes.c_int32),
+                ("restart_passes", ctypes.c_int32)]
 
 
 _lib = None
@@ -117,12 +118,13 @@ def _check(code: int, what: str):
 
 
 def make_opts(f=1, a_mode=0, reduce_mode=0, transform_mode=0, withhold_driver=0,
-              check_workspace=0) -> wallace_opts:
+              check_workspace=0, restart_passes=0) -> wallace_opts:
     o = wallace_opts()
     lib().wallace_default_opts(ctypes.byref(o))
     o.f, o.a_mode, o.reduce_mode = f, a_mode, reduce_mode
     o.transform_mode, o.withhold_driver, o.check_workspace = (
         transform_mode, withhold_driver, check_workspace)
+    o.restart_passes = restart_passes
     return o
 
 

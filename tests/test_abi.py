@@ -47,7 +47,7 @@ def test_strerror_and_defaults():
     assert "workspace" in W.strerror(W.WALLACE_ENOSPC)
     o = W.make_opts()
     assert (o.f, o.a_mode, o.reduce_mode, o.transform_mode, o.withhold_driver,
-            o.check_workspace) == (1, 0, 0, 0, 0, 0)
+            o.check_workspace, o.restart_passes) == (1, 0, 0, 0, 0, 0, 0)
 
 
 @pytest.mark.parametrize("n,N,ok", [(4, 4, True), (4, 1024, True), (16, 16, True),
@@ -81,6 +81,10 @@ def test_init_argument_errors_before_gpu():
     assert L.wallace_init(1, 4, 64, ctypes.byref(bad), 4096, 1 << 20, None, ctypes.byref(h)) == W.WALLACE_EINVAL
     bad = W.make_opts(reduce_mode=3)
     assert L.wallace_init(1, 4, 64, ctypes.byref(bad), 4096, 1 << 20, None, ctypes.byref(h)) == W.WALLACE_EINVAL
+    bad = W.make_opts(f=3, restart_passes=10)  # restart interval must be a multiple of f
+    assert L.wallace_init(1, 4, 64, ctypes.byref(bad), 4096, 1 << 20, None, ctypes.byref(h)) == W.WALLACE_EINVAL
+    bad = W.make_opts(restart_passes=-1)
+    assert L.wallace_init(1, 4, 64, ctypes.byref(bad), 4096, 1 << 20, None, ctypes.byref(h)) == W.WALLACE_EINVAL
     mm = W.make_opts(transform_mode=1)  # matrix cores only for n = 16
     assert L.wallace_init(1, 4, 1 << 20, ctypes.byref(mm), 4096, 1 << 40, None, ctypes.byref(h)) == W.WALLACE_EUNSUP
     # ... and for streamed pools of one tuple per thread (n = 16, 2^13 <= N <= 2^20)
@@ -110,6 +114,12 @@ def test_batch_workspace_validation():
     assert L.wallace_batch_workspace_bytes(3, n.ctypes.data, N2.ctypes.data, ctypes.byref(b)) == W.WALLACE_EINVAL
     N3 = np.array([256, 64, 1 << 20], dtype=np.uint32)  # too large to stay on chip
     assert L.wallace_batch_workspace_bytes(3, n.ctypes.data, N3.ctypes.data, ctypes.byref(b)) == W.WALLACE_EUNSUP
+    # restarts are for single generators only (checked before the GPU)
+    seeds = np.arange(3, dtype=np.uint64)
+    o = W.make_opts(restart_passes=8)
+    h = ctypes.c_void_p()
+    assert L.wallace_batch_init(3, seeds.ctypes.data, n.ctypes.data, N.ctypes.data, ctypes.byref(o),
+                                256, 1 << 30, None, ctypes.byref(h)) == W.WALLACE_EUNSUP
 
 
 @pytest.mark.parametrize("seed,n,N", [(42, 4, 1024), (0, 4, 4), (7, 16, 16),

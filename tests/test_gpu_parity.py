@@ -249,3 +249,34 @@ def test_mfma_transform_accuracy():
     print(f"mfma max err {err.max():.3g}, butterflies {err32.max():.3g}", flush=True)
     assert err.max() <= 1e-5
     assert np.any(got.view(np.uint32) != ref32.view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# restarts (section 5): Box-Muller refill on the GPU
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,N,R,f,counts", [
+    (4, 1024, 10, 1, [4096 * 35]),
+    (4, 1024, 10, 1, [4096 * 9 + 7, 4096 * 13, 4096 * 13 - 7]),
+    (4, 256, 4, 2, [1024 * 9]),
+    (2, 512, 6, 3, [1024 * 7]),
+    (4, 1 << 15, 4, 1, [(1 << 17) * 10]),
+    (16, 1 << 13, 3, 1, [(1 << 17) * 7]),
+])
+def test_restart_refills(n, N, R, f, counts):
+    # The refill uses the GPU's FP64 log, cos and sin, the oracle the host's
+    # libm: a refilled value can differ in its last bit, and the passes after
+    # it then stay within FP32 rounding of the oracle. Everything else is
+    # bit-exact.
+    _dev()
+    print(f"case restart n={n} N={N} R={R} f={f}", flush=True)
+    g = W.Generator(17, n, N, restart_passes=R, f=f)
+    got = gpu_stream(g, counts)
+    ref_gen = oracle.Gen(17, n, N, restart=R, f=f)
+    ref = ref_gen.fill(sum(counts))
+    same = np.mean(got.view(np.uint32) == ref.view(np.uint32))
+    err = np.abs(got.astype(np.float64) - ref) / np.maximum(1.0, np.abs(ref))
+    print(f"restart: identical words {same:.6f}, max error {err.max():.3g}", flush=True)
+    assert same >= 0.999 and err.max() <= 1e-5
+    _, passes = g.sumsq()
+    assert passes == ref_gen.passes

@@ -141,6 +141,26 @@ def test_normal_epilogue():
     assert_bits_equal(out.cpu().numpy(), ref.astype(np.float32), "mu + sigma x")
 
 
+@pytest.mark.parametrize("n,N", [(4, 1 << 15), (2, 1 << 15)])
+def test_normal_epilogue_streamed(n, N):
+    # streamed pools write mu + sigma x to the output and keep the pool in the
+    # workspace (a scaled output cannot be the next pass's old pool)
+    _dev()
+    g = W.Generator(5, n, N)
+    total = n * N * 3 + 11
+    out = torch.empty(total, dtype=torch.float32, device="cuda")
+    g.fill_normal(out, -1.25, 2.0)
+    x = oracle.Gen(5, n, N).fill(total)
+    ref = np.float32(-1.25) + np.float32(2.0) * x
+    assert_bits_equal(out.cpu().numpy(), ref.astype(np.float32), "streamed mu + sigma x")
+    # and the stream continues unscaled from the same state
+    out2 = torch.empty(n * N, dtype=torch.float32, device="cuda")
+    g.fill(out2)
+    ref_gen = oracle.Gen(5, n, N)
+    ref_gen.fill(total)
+    assert_bits_equal(out2.cpu().numpy(), ref_gen.fill(n * N), "continued stream")
+
+
 def test_corruption_is_detected():
     # Section 8 footnote: a large change in the sum of squares means the work
     # area was overwritten. Force it from the host: overwrite pool bytes.
@@ -153,6 +173,24 @@ def test_corruption_is_detected():
     base = g._ws_ptr - ws.data_ptr()
     pool_off = 512  # header (256) + state, aligned to 256
     ws[base + pool_off: base + pool_off + 64] = 0x3F
+    g.fill(out)
+    rc, flags = g.status()
+    assert rc == W.WALLACE_ECORRUPT and flags & W.FLAG_CORRUPT
+
+
+def test_corruption_is_detected_streamed():
+    # a streamed pool is checked by the tree kernels at the start of a call
+    _dev()
+    n, N = 4, 1 << 15
+    nu = n * N
+    g = W.Generator(4, n, N, check_workspace=1)
+    out = torch.empty(nu * 3, dtype=torch.float32, device="cuda")
+    g.fill(out)
+    assert g.status() == (0, 0)
+    ws = g.workspace
+    base = g._ws_ptr - ws.data_ptr()
+    pool_off = 512  # header (256) + state, aligned to 256; both pool buffers follow
+    ws[base + pool_off: base + pool_off + 2 * nu * 4] = 0x3F
     g.fill(out)
     rc, flags = g.status()
     assert rc == W.WALLACE_ECORRUPT and flags & W.FLAG_CORRUPT

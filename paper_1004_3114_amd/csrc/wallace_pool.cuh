@@ -344,18 +344,24 @@ struct Cfg {
     static constexpr int BLOCK = MW ? L : 256;
     static constexpr int W = MW ? L / 64 : 1;      // waves per group
     using Nd = typename NodeOf<RM>::type;
-    // Small components are stored twice in a row in LDS, so the gather
-    // address x0 + d with x0, d < N needs no wrap-around.
-    static constexpr bool DUP = C * N <= 2048;
+    // One stage (the whole pool fits): the pool lives in LDS between passes
+    // (run_job_lds). Several stages: it lives in registers (run_job).
+    static constexpr bool LDSRES = NST == 1;
+    // Register-resident form only: small components are stored twice in a
+    // row in LDS, so the gather address x0 + d with x0, d < N needs no wrap.
+    static constexpr bool DUP = !LDSRES && C * N <= 2048;
     static constexpr int CSTRIDE = DUP ? 2 * N : N;  // floats between components
-    // single-wave groups reuse their permutation-network space for the
-    // reduction transpose (n*L nodes)
     static constexpr int POOL_BYTES = C * CSTRIDE * 4;
-    static constexpr int RED_BYTES = MW ? 0 : NC * L * Nd::kBytes;
+    // register-resident single-wave groups reuse their permutation-network
+    // space for the reduction transpose (n*L nodes)
+    static constexpr int RED_BYTES = (MW || LDSRES) ? 0 : NC * L * Nd::kBytes;
     static constexpr int GROUP_RAW = POOL_BYTES > RED_BYTES ? POOL_BYTES : RED_BYTES;
-    // multiple of 4N bytes, so a component's offset can be or-ed into an
-    // address masked to 4N - 4
-    static constexpr int GROUP_BYTES = (GROUP_RAW + 4 * N - 1) / (4 * N) * (4 * N);
+    // LDS-resident groups sharing a wave are L words apart in bank terms, so
+    // their lanes use different banks; register-resident ones are padded to a
+    // multiple of 4N bytes
+    static constexpr int GROUP_BYTES =
+        LDSRES ? POOL_BYTES + (L < 64 ? 4 * L : 0)
+               : (GROUP_RAW + 4 * N - 1) / (4 * N) * (4 * N);
     static constexpr int CH = L >= 64 ? 64 : L;  // passes per parameter chunk
     static constexpr int XW_BYTES = MW ? 16 * W * NC : 0;  // cross-wave nodes
     static constexpr int LDS_BYTES = GPB * GROUP_BYTES + XW_BYTES;
@@ -413,6 +419,26 @@ __device__ __forceinline__ double pool_sumsq(const float (&X)[NC][T], int lane, 
         // lanes 0..NC-1 of every wave now hold the total; lane 0 is uniform
         return acc.uniform().value();
     }
+}
+
+// Sum of squares of a pool held by a group of at most one wave, in registers
+// only: the same halving as the multi-wave path (each exchange level joins
+// lane pairs in tree order while the lanes split the components), then the
+// remaining lane levels and the component levels. Every lane of the group
+// ends with the total.
+template <int NC, int T, int L, int RM>
+__device__ __forceinline__ double pool_sumsq_regs(const float (&X)[NC][T], int lane)
+{
+    using Nd = typename NodeOf<RM>::type;
+    static_assert(L <= 64 && L >= NC, "one wave or less, at least n lanes");
+    Nd v[16];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) v[k] = lane_tree<Nd, T>(X[k]);
+    const int wl = lane & 63;
+    halve_all<Nd, 1, NC>(v, wl);
+    Nd acc = butterfly<Nd, NC, L>(v[0]);
+    acc = comp_levels<Nd, NC / 2>(acc);
+    return (L >= 64 ? acc.uniform() : acc).value();
 }
 
 // n = 4: A0 = H4/2 (mat 0) and A1 = J/2 - I (mat 1) with
@@ -744,6 +770,183 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
     }
 }
 
+// One job with the pool resident in LDS between passes (one stage). Each
+// pass: lane l gathers tuples j = l + L*i (i < T) from the old pool's LDS
+// image; consecutive lanes then read addresses a apart (a odd), which hits
+// distinct banks. The new pool overwrites the image in the same tuple
+// order; the lanes read it back as T consecutive tuples each (the order of
+// the output and of the sum-of-squares tree) for emission and the sum of
+// squares.
+template <int NC, int T, int L, int RM>
+__device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char *xw, int lane)
+{
+    using Cf = Cfg<NC, T, L, RM, 1>;
+    constexpr int N = Cf::N;
+    constexpr int CH = Cf::CH;
+    constexpr bool MW = Cf::MW;
+    constexpr uint32_t nu = (uint32_t)(NC * N);
+    constexpr uint32_t amask = 4u * (uint32_t)N - 4u;
+    static_assert(N <= (1 << 14), "packed parameters need N <= 2^14");
+
+    GenState *stp = P.states + job.gen;
+    const uint64_t rng0 = stp->rng;
+    double sigma = stp->sigma;
+    const uint64_t done = stp->passes;
+    uint32_t flags = stp->flags;
+
+    auto sumsq = [&](const float (&Z)[NC][T]) -> double {
+        if constexpr (MW)
+            return pool_sumsq<NC, T, L, RM, 1>(Z, lane, nullptr, xw);
+        else
+            return pool_sumsq_regs<NC, T, L, RM>(Z, lane);
+    };
+
+    {
+        float Z[NC][T];
+        const float *pool = P.pools + job.pool_off;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) load_run<T>(Z[k], pool + k * N + T * lane);
+        if (P.sigma_mode) {
+            const double s = sumsq(Z);
+            if (P.sigma_mode == 2)
+                sigma = s;
+            else if (!(s == sigma))
+                flags |= WALLACE_FLAG_CORRUPT;
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) store_lds<T>(lds + k * N + T * lane, Z[k]);
+    }
+    group_sync<MW>();
+    const uint32_t passes = (flags & WALLACE_FLAG_CORRUPT) ? 0u : job.passes;
+    const uint32_t qlane = (uint32_t)lane % (uint32_t)CH;
+
+    uint32_t words[NC];
+    uint32_t swords = 0;
+    double rcs = 0.0, rsn = 0.0;
+    uint32_t slot = 0;
+    auto draw_chunk = [&](uint32_t ps0) {
+        swords = 0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            words[k] = pass_word<NC, N>(rng0, ps0 + qlane, k, P.a_mode, &swords);
+        if constexpr (NC == 2) {
+            const uint64_t m = 3ull * (ps0 + qlane) + 3ull;
+            rotation(sm64_mix(rng0 + m * kGamma), rcs, rsn);
+        }
+        slot = 0;
+    };
+    uint32_t fcount = 0;
+    uint32_t emitted = 0;
+
+    auto one_pass = [&](uint32_t ps, auto mat_c) {
+        constexpr int MAT = decltype(mat_c)::value;
+        const uint32_t signs = NC == 16 ? bcast<L>(swords, slot) : 0u;
+        double cs = 0.0, sn = 0.0;
+        if constexpr (NC == 2) {
+            cs = __hiloint2double((int)bcast<L>((uint32_t)__double2hiint(rcs), slot),
+                                  (int)bcast<L>((uint32_t)__double2loint(rcs), slot));
+            sn = __hiloint2double((int)bcast<L>((uint32_t)__double2hiint(rsn), slot),
+                                  (int)bcast<L>((uint32_t)__double2loint(rsn), slot));
+        }
+        // the old pool's last flat value (section 4)
+        const double xstar = (double)lds[(NC - 1) * N + (N - 1)];
+        float V[NC][T];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const uint32_t wd = bcast<L>(words[k], slot);
+            const uint32_t a4 = wd & 0xFFFFu, b4 = wd >> 16;
+            const char *src = reinterpret_cast<const char *>(lds + k * N);
+            // 4 ((a j + b) mod N) for j = l + L i: x0 + 4 (a L i mod N)
+            const uint32_t x0 = (__umul24(a4, (uint32_t)lane) + b4) & amask;
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                const uint32_t d4 = (a4 * (uint32_t)(L * i)) & amask;  // wave-uniform
+                V[k][i] = *reinterpret_cast<const float *>(src + ((x0 + d4) & amask));
+            }
+        }
+        ++slot;
+
+        const double c64 = chi2_scale64(xstar, sigma, P.r_nu);
+        const float c32 = (float)c64;
+        if (!__builtin_isfinite(c32)) flags |= WALLACE_FLAG_NONFINITE;
+        const float h = c32 * (NC == 4 ? 0.5f : 0.25f);
+        const float rp = NC == 2 ? (float)(c64 * cs) : 0.0f;
+        const float rq = NC == 2 ? (float)(c64 * sn) : 0.0f;
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            float v[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) v[k] = V[k][i];
+            if constexpr (NC == 4)
+                xform4(v, MAT, h);
+            else if constexpr (NC == 2)
+                xform2(v, rp, rq);
+            else
+                xform16(v, signs, h);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) V[k][i] = v[k];
+        }
+
+        group_sync<MW>();  // every gather of the old image is done
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+#pragma unroll
+            for (int i = 0; i < T; ++i) lds[k * N + lane + L * i] = V[k][i];
+        }
+        group_sync<MW>();
+        float Z[NC][T];  // the new pool, T consecutive tuples per lane
+#pragma unroll
+        for (int k = 0; k < NC; ++k) load_run<T>(Z[k], lds + k * N + T * lane);
+
+        if (++fcount == P.f) {  // a returned pool (section 6)
+            fcount = 0;
+            const bool last = (ps + 1 == passes);
+            const uint32_t cnt = last ? job.last_emit : P.emit_len;
+            float *base = P.out + job.out_off + (uint64_t)emitted * P.emit_len;
+            ++emitted;
+            constexpr uintptr_t vmask = (uintptr_t)(4 * (T >= 4 ? 4 : T) - 1);
+            if (cnt == nu && ((uintptr_t)base & vmask) == 0 && !P.affine) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) store_run<T>(base + k * N + T * lane, Z[k], true);
+            } else {
+                emit_slow<NC, T, N>(Z, base, cnt, lane, P.affine, P.mu, P.sigma_out);
+            }
+        }
+        sigma = sumsq(Z);
+    };
+
+    using M0 = std::integral_constant<int, 0>;
+    using M1 = std::integral_constant<int, NC == 4 ? 1 : 0>;
+    const bool odd = NC == 4 && (done & 1u);
+    for (uint32_t c0 = 0; c0 < passes; c0 += (uint32_t)CH) {
+        const uint32_t end = passes - c0 < (uint32_t)CH ? passes : c0 + (uint32_t)CH;
+        draw_chunk(c0);
+        uint32_t ps = c0;
+        if (odd) one_pass(ps++, M1());
+        for (; ps + 2 <= end; ps += 2) {
+            one_pass(ps, M0());
+            one_pass(ps + 1, M1());
+        }
+        if (ps < end) one_pass(ps, M0());
+    }
+
+    // the final pool from its LDS image
+    float *wpool = P.pools + job.pool_off;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        float Z[T];
+        load_run<T>(Z, lds + k * N + T * lane);
+        store_run<T>(wpool + k * N + T * lane, Z, false);
+    }
+    group_sync<MW>();  // the next job of this group reuses the LDS image
+    if (lane == 0) {
+        stp->rng = rng0 + (uint64_t)Draws<NC>::value * passes * kGamma;
+        stp->sigma = sigma;
+        stp->passes = done + passes;
+        stp->flags = flags;
+    }
+}
+
 template <int NC, int T, int L, int RM, int NST>
 __global__ __launch_bounds__((L > 64 ? L : 256)) void k_pool(PoolArgs P)
 {
@@ -758,7 +961,10 @@ __global__ __launch_bounds__((L > 64 ? L : 256)) void k_pool(PoolArgs P)
     if constexpr (Cf::UNIFORM) j = __builtin_amdgcn_readfirstlane(j);
     for (; j < P.njobs; j += total) {
         const Job job = P.jobs ? P.jobs[j] : P.one;
-        run_job<NC, T, L, RM, NST>(P, job, lds, xw, lane);
+        if constexpr (Cf::LDSRES)
+            run_job_lds<NC, T, L, RM>(P, job, lds, xw, lane);
+        else
+            run_job<NC, T, L, RM, NST>(P, job, lds, xw, lane);
     }
 }
 

@@ -13,18 +13,20 @@
 //   in flat order f = k*N + j (section 3), and its sum of squares is formed
 //   for the next pass (section 4).
 //
-// A group of L lanes owns one pool for a whole job and keeps it in registers:
-// lane l holds tuples T*l .. T*l+T-1 of every component. LDS is the per-pass
-// permutation network, C = n/NST components at a time, each component stored
-// in natural order (a lane writes its T values with one vector store). Small
-// components are stored twice back to back: a lane's T gathers then share
-// one base address (a j0 + b) mod N and add the wave-uniform a i mod N, with
-// no wrap-around per value. The
-// per-pass draws are counter-based (splitmix64 draw m is a function of
-// state + m * gamma), so each lane computes one pass's parameters for a chunk
-// of up to 64 passes at once and every pass reads its parameters with one
-// lane read per component. T and L are compile-time, so every LDS and store
-// offset is an immediate.
+// A group of L lanes owns one pool for a whole job. When the pool fits in
+// the group's LDS share (every shape with one stage) it lives there between
+// passes: lane l gathers tuples j = l + L*i (i < T), so the lanes of a wave
+// read L consecutive multiples of the stride, which fall in distinct banks;
+// the new values overwrite the image in place, and the lane then reads back
+// tuples T*l .. T*l+T-1 with vector loads for the store to HBM and the sum of
+// squares (run_job_lds). Larger pools (multi-wave groups only) live in
+// registers, lane l holding tuples T*l .. T*l+T-1 of every component, and
+// LDS is the per-pass permutation network, C = n/NST components at a time
+// (run_job). The per-pass draws are counter-based (splitmix64 draw m is a
+// function of state + m * gamma), so each lane computes one pass's
+// parameters for a chunk of up to 64 passes at once and every pass reads its
+// parameters with one lane read per component. T and L are compile-time, so
+// every LDS and store offset is an immediate.
 //
 // Bit-exactness: no FMA contraction (-ffp-contract=off), butterflies in a
 // fixed order, and the sum of squares as the canonical pairwise tree over
@@ -345,80 +347,56 @@ struct Cfg {
     static constexpr int W = MW ? L / 64 : 1;      // waves per group
     using Nd = typename NodeOf<RM>::type;
     // One stage (the whole pool fits): the pool lives in LDS between passes
-    // (run_job_lds). Several stages: it lives in registers (run_job).
+    // (run_job_lds). Several stages (only multi-wave groups with pools over
+    // 128 KiB): it lives in registers and LDS holds C components at a time
+    // (run_job).
     static constexpr bool LDSRES = NST == 1;
-    // Register-resident form only: small components are stored twice in a
-    // row in LDS, so the gather address x0 + d with x0, d < N needs no wrap.
-    static constexpr bool DUP = !LDSRES && C * N <= 2048;
-    static constexpr int CSTRIDE = DUP ? 2 * N : N;  // floats between components
-    static constexpr int POOL_BYTES = C * CSTRIDE * 4;
-    // register-resident single-wave groups reuse their permutation-network
-    // space for the reduction transpose (n*L nodes)
-    static constexpr int RED_BYTES = (MW || LDSRES) ? 0 : NC * L * Nd::kBytes;
-    static constexpr int GROUP_RAW = POOL_BYTES > RED_BYTES ? POOL_BYTES : RED_BYTES;
-    // LDS-resident groups sharing a wave are L words apart in bank terms, so
-    // their lanes use different banks; register-resident ones are padded to a
-    // multiple of 4N bytes
-    static constexpr int GROUP_BYTES =
-        LDSRES ? POOL_BYTES + (L < 64 ? 4 * L : 0)
-               : (GROUP_RAW + 4 * N - 1) / (4 * N) * (4 * N);
+    static_assert(LDSRES || MW, "several stages only for multi-wave groups");
+    static constexpr int POOL_BYTES = C * N * 4;
+    // groups sharing a wave start L words apart in bank terms, so their
+    // lanes use different banks
+    static constexpr int GROUP_BYTES = POOL_BYTES + (L < 64 ? 4 * L : 0);
     static constexpr int CH = L >= 64 ? 64 : L;  // passes per parameter chunk
     static constexpr int XW_BYTES = MW ? 16 * W * NC : 0;  // cross-wave nodes
     static constexpr int LDS_BYTES = GPB * GROUP_BYTES + XW_BYTES;
 };
 
-// Sum of squares of a pool held by a group (see the file comment).
+// Sum of squares of a pool held by a multi-wave group: per lane a tree over
+// its T consecutive values of each component; within each wave the halving
+// levels (each joins lane pairs in tree order while the lanes split the
+// components) and the remaining lane levels; then the waves' nodes in order
+// through LDS, and the component levels.
 template <int NC, int T, int L, int RM, int NST>
-__device__ __forceinline__ double pool_sumsq(const float (&X)[NC][T], int lane, char *grp_lds,
-                                             char *xw_lds)
+__device__ __forceinline__ double pool_sumsq(const float (&X)[NC][T], int lane, char *xw_lds)
 {
     using C = Cfg<NC, T, L, RM, NST>;
     using Nd = typename C::Nd;
+    static_assert(C::MW, "multi-wave groups; pool_sumsq_regs serves one wave or less");
     constexpr int LOG_NC = Log2<NC>::value;
     Nd v[16];
 #pragma unroll
     for (int k = 0; k < NC; ++k) v[k] = lane_tree<Nd, T>(X[k]);
-    if constexpr (!C::MW) {
-        // transpose through LDS: node (k, lane) -> flat slot k*L + lane; then
-        // lane m owns slots NC*m .. NC*m+NC-1, joins them in tree order and
-        // the lanes finish with a butterfly
-        group_sync<false>();
+    const int wl = lane & 63;
+    const int wave = lane >> 6;
+    halve_all<Nd, 1, NC>(v, wl);
+    Nd acc = butterfly<Nd, NC, 64>(v[0]);
+    int kappa = 0;
 #pragma unroll
-        for (int k = 0; k < NC; ++k) v[k].put(grp_lds + (k * L + lane) * Nd::kBytes);
-        group_sync<false>();
-        Nd t[NC];
+    for (int m = 0; m < LOG_NC; ++m) kappa |= ((wl >> m) & 1) << (LOG_NC - 1 - m);
+    group_sync<true>();  // earlier readers of the cross-wave area are done
+    if (wl < NC) acc.put(xw_lds + (wave * NC + kappa) * 16);
+    group_sync<true>();
+    Nd t[C::W];
 #pragma unroll
-        for (int q = 0; q < NC; ++q) t[q] = Nd::get(grp_lds + (NC * lane + q) * Nd::kBytes);
+    for (int w = 0; w < C::W; ++w) t[w] = Nd::get(xw_lds + (w * NC + kappa) * 16);
 #pragma unroll
-        for (int w = NC; w > 1; w >>= 1) {
+    for (int s = C::W; s > 1; s >>= 1) {
 #pragma unroll
-            for (int i = 0; i < w / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
-        }
-        const Nd r = butterfly<Nd, 1, L>(t[0]);
-        return (C::UNIFORM ? r.uniform() : r).value();
-    } else {
-        const int wl = lane & 63;
-        const int wave = lane >> 6;
-        halve_all<Nd, 1, NC>(v, wl);
-        Nd acc = butterfly<Nd, NC, 64>(v[0]);
-        int kappa = 0;
-#pragma unroll
-        for (int m = 0; m < LOG_NC; ++m) kappa |= ((wl >> m) & 1) << (LOG_NC - 1 - m);
-        group_sync<true>();  // earlier readers of the cross-wave area are done
-        if (wl < NC) acc.put(xw_lds + (wave * NC + kappa) * 16);
-        group_sync<true>();
-        Nd t[C::W];
-#pragma unroll
-        for (int w = 0; w < C::W; ++w) t[w] = Nd::get(xw_lds + (w * NC + kappa) * 16);
-#pragma unroll
-        for (int s = C::W; s > 1; s >>= 1) {
-#pragma unroll
-            for (int i = 0; i < s / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
-        }
-        acc = comp_levels<Nd, NC / 2>(t[0]);
-        // lanes 0..NC-1 of every wave now hold the total; lane 0 is uniform
-        return acc.uniform().value();
+        for (int i = 0; i < s / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
     }
+    acc = comp_levels<Nd, NC / 2>(t[0]);
+    // lanes 0..NC-1 of every wave now hold the total; lane 0 is uniform
+    return acc.uniform().value();
 }
 
 // Sum of squares of a pool held by a group of at most one wave, in registers
@@ -600,12 +578,10 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
     constexpr int N = Cf::N;
     constexpr int C = Cf::C;
     constexpr int CH = Cf::CH;
-    constexpr int CS = Cf::CSTRIDE;
     constexpr bool MW = Cf::MW;
     constexpr uint32_t nu = (uint32_t)(NC * N);
     constexpr uint32_t amask = 4u * (uint32_t)N - 4u;
     static_assert(N <= (1 << 14), "packed parameters need N <= 2^14");
-    char *grp_bytes = reinterpret_cast<char *>(lds);
 
     float X[NC][T];
     const float *pool = P.pools + job.pool_off;
@@ -619,7 +595,7 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
     uint32_t flags = stp->flags;
 
     if (P.sigma_mode) {
-        const double s = pool_sumsq<NC, T, L, RM, NST>(X, lane, grp_bytes, xw);
+        const double s = pool_sumsq<NC, T, L, RM, NST>(X, lane, xw);
         if (P.sigma_mode == 2)
             sigma = s;
         else if (!(s == sigma))
@@ -665,34 +641,20 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
         for (int st = 0; st < NST; ++st) {
             group_sync<MW>();  // previous readers of this LDS space are done
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                store_lds<T>(lds + c * CS + T * lane, X[st * C + c]);
-                if constexpr (Cf::DUP) store_lds<T>(lds + c * CS + N + T * lane, X[st * C + c]);
-            }
+            for (int c = 0; c < C; ++c) store_lds<T>(lds + c * N + T * lane, X[st * C + c]);
             group_sync<MW>();
             if (st == NST - 1)  // the old pool's last flat value (section 4)
-                xstar = (double)lds[(C - 1) * CS + (N - 1)];
+                xstar = (double)lds[(C - 1) * N + (N - 1)];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const uint32_t wd = bcast<L>(words[st * C + c], slot);
                 const uint32_t a4 = wd & 0xFFFFu, b4 = wd >> 16;
-                const char *src = reinterpret_cast<const char *>(lds + c * CS);
-                if constexpr (Cf::DUP) {
-                    // 4 * ((a j + b) mod N) = x0 + 4 * (a i mod N) - (0 or 4N),
-                    // and the second image absorbs the 4N
-                    const uint32_t x0 = (__umul24(a4, j0) + b4) & amask;
+                const char *src = reinterpret_cast<const char *>(lds + c * N);
 #pragma unroll
-                    for (int i = 0; i < T; ++i) {
-                        const uint32_t d4 = (a4 * (uint32_t)i) & amask;  // wave-uniform
-                        X[st * C + c][i] = *reinterpret_cast<const float *>(src + x0 + d4);
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < T; ++i) {
-                        // 4 * ((a j + b) mod N) for tuple j = T*lane + i
-                        const uint32_t x4 = (__umul24(a4, j0 + i) + b4) & amask;
-                        X[st * C + c][i] = *reinterpret_cast<const float *>(src + x4);
-                    }
+                for (int i = 0; i < T; ++i) {
+                    // 4 * ((a j + b) mod N) for tuple j = T*lane + i
+                    const uint32_t x4 = (__umul24(a4, j0 + i) + b4) & amask;
+                    X[st * C + c][i] = *reinterpret_cast<const float *>(src + x4);
                 }
             }
         }
@@ -737,7 +699,7 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
             }
         }
 
-        sigma = pool_sumsq<NC, T, L, RM, NST>(X, lane, grp_bytes, xw);
+        sigma = pool_sumsq<NC, T, L, RM, NST>(X, lane, xw);
     };
 
     // Chunks of CH passes (CH is even, so every chunk starts on the same
@@ -796,7 +758,7 @@ __device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char 
 
     auto sumsq = [&](const float (&Z)[NC][T]) -> double {
         if constexpr (MW)
-            return pool_sumsq<NC, T, L, RM, 1>(Z, lane, nullptr, xw);
+            return pool_sumsq<NC, T, L, RM, 1>(Z, lane, xw);
         else
             return pool_sumsq_regs<NC, T, L, RM>(Z, lane);
     };

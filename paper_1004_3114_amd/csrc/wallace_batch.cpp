@@ -244,7 +244,12 @@ int32_t wallace_batch_init(uint32_t G, const uint64_t *seeds, const int32_t *n,
             ClassInfo c;
             c.n = n[g];
             c.N = N[g];
-            if (!tuned_sched(c.n, c.N, &c.sched)) default_sched(c.n, c.N, &c.sched);
+            const int found = tuned_sched(c.n, c.N, &c.sched);
+            if (found < 0) {  // WALLACE_SCHED names a shape that is not compiled
+                delete b;
+                return WALLACE_EINVAL;
+            }
+            if (found == 0) default_sched(c.n, c.N, &c.sched);
             index[key] = b->classes.size();
             b->classes.push_back(c);
             it = index.find(key);

@@ -279,10 +279,12 @@ int32_t wallace_init(uint64_t seed, int32_t n, uint32_t N,
     g->streaming = !default_sched(n, N, &g->sched);
     if (!g->streaming) {
         Sched t{};
-        if (forced_sched(n, N, &t))  // WALLACE_SCHED
-            g->sched = t;
-        else if (single_sched(n, N, &t))
-            g->sched = t;
+        const int forced = forced_sched(n, N, &t);  // WALLACE_SCHED
+        if (forced < 0) {  // names a shape that is not compiled
+            delete g;
+            return WALLACE_EINVAL;
+        }
+        if (forced > 0 || single_sched(n, N, &t)) g->sched = t;
     }
     g->passes_host = 0;
     if ((o.transform_mode == 1 && !g->streaming) || (g->streaming && !stream_shape_ok(n, N, o.transform_mode))) {

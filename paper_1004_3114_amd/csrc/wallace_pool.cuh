@@ -352,6 +352,12 @@ struct Cfg {
     // (run_job).
     static constexpr bool LDSRES = NST == 1;
     static_assert(LDSRES || MW, "several stages only for multi-wave groups");
+    // swizzled stage images (register-resident form; see swz4)
+    static constexpr bool SWZ = !LDSRES && T >= 2;
+    // register-resident with more than 4 tuples per lane: the output goes
+    // through wave-private LDS slices (emit_transposed)
+    static constexpr bool EMIT_LDS = !LDSRES && T > 4;
+    static_assert(!EMIT_LDS || C * N >= 64 * T * (L / 64) * C, "slices fit the stage area");
     static constexpr int POOL_BYTES = C * N * 4;
     // groups sharing a wave start L words apart in bank terms, so their
     // lanes use different banks
@@ -522,6 +528,85 @@ __device__ __forceinline__ void store_lds(float *p, const float (&x)[T])
     }
 }
 
+// Stage images of the register-resident form keep word x of a component at
+// x ^ ((x >> 6) & (T - 1)). A wave's gather reads words a*T apart (a odd):
+// without the swizzle only 64/T banks would serve the 64 lanes; with it
+// every lane of a 64-word row group lands in its own bank. The swizzle stays
+// inside T-word blocks, so a lane's T values remain in its own block.
+// Byte-address form: x4 = 4x.
+template <int T>
+__device__ __forceinline__ uint32_t swz4(uint32_t x4)
+{
+    return x4 ^ ((x4 >> 6) & (uint32_t)(4 * (T - 1)));
+}
+
+// A lane's T consecutive values into a swizzled stage image; blk4 is the
+// byte offset of the lane's block with the swizzle applied to its first
+// word (the swizzle of word B + t is (B + sw) ^ t for the block base B).
+template <int T>
+__device__ __forceinline__ void store_lds_swz(char *comp, uint32_t blk4, const float (&x)[T])
+{
+#pragma unroll
+    for (int t = 0; t < T; ++t) *reinterpret_cast<float *>(comp + (blk4 ^ (uint32_t)(4 * t))) = x[t];
+}
+
+// Output of the new pool of a multi-wave group whose lanes hold T > 4
+// consecutive values per component. Stored straight from registers, each
+// store instruction of a wave would be lane-strided (T*4 bytes between
+// lanes), a pattern that streams several times slower than consecutive
+// chunks. Instead each wave passes its values through a private slice of
+// the stage area (64*T floats per component, free once every gather of the
+// pass is done) and reads them back transposed: store instruction s of a
+// wave covers its 16-byte chunks 64*s .. 64*s + 63, 1 KB of consecutive
+// output. Chunk c of a slice sits in slot c ^ ((c >> 4) & (Q - 1)), which
+// keeps the 16 lanes of each quarter-wave in distinct slots mod 16 both
+// when writing (c = Q*lane + q) and when reading (c = 64*s + lane). Slices
+// are wave-private and LDS operations of a wave complete in order, so the C
+// components of one round and the rounds after it need no barrier.
+template <int NC, int T, int C, int N>
+__device__ __forceinline__ void emit_transposed(const float (&X)[NC][T], float *out, char *lds,
+                                                uint32_t ln)
+{
+    static_assert(T % 4 == 0 && T > 4, "whole chunks, more than one per lane");
+    constexpr int Q = T / 4;                  // 16-byte chunks per lane and component
+    constexpr uint32_t SL = 64u * T * 4u;      // bytes of one slice
+    const uint32_t w = ln >> 6, wl = ln & 63u;
+    auto slot = [](uint32_t c) { return c ^ ((c >> 4) & (uint32_t)(Q - 1)); };
+#pragma unroll
+    for (int r = 0; r < NC / C; ++r) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            char *sl = lds + (w * (uint32_t)C + (uint32_t)c) * SL;
+            const float(&x)[T] = X[r * C + c];
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                *reinterpret_cast<v4f *>(sl + 16u * slot((uint32_t)Q * wl + (uint32_t)q)) =
+                    v4f{x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]};
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const char *sl = lds + (w * (uint32_t)C + (uint32_t)c) * SL;
+            // the wave's tuples start at 64*T*w
+            v4f *o = reinterpret_cast<v4f *>(out + (r * C + c) * N + 64u * T * w);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const uint32_t k = 64u * (uint32_t)q + wl;
+                __builtin_nontemporal_store(*reinterpret_cast<const v4f *>(sl + 16u * slot(k)), o + k);
+            }
+        }
+    }
+}
+
+// Compile-time loop: f(integral_constant<int, I>) for I in [B, E).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>());
+        static_for<B + 1, E>(f);
+    }
+}
+
 // Element-wise emission: partial pools, unaligned outputs, N(mu, sigma^2).
 // One base address per component; the T values of a lane are immediate
 // offsets from it, and value i is inside the emitted prefix iff i < lim.
@@ -603,7 +688,6 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
     }
     const uint32_t passes = (flags & WALLACE_FLAG_CORRUPT) ? 0u : job.passes;
     const uint32_t qlane = (uint32_t)lane % (uint32_t)CH;  // pass slot this lane computes
-    const uint32_t j0 = (uint32_t)(T * lane);               // first tuple of this lane
 
     uint32_t words[NC];  // packed (4a, 4b) of pass chunk + qlane, per component
     uint32_t swords = 0; // column signs of that pass (n = 16)
@@ -627,6 +711,14 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
     // One pass with the matrix fixed at compile time (n = 4 alternates A0
     // and A1; a uniform branch picks the body, so no per-value selects).
     auto one_pass = [&](uint32_t ps, auto mat_c) {
+        // The lane index is made opaque once per pass, so the compiler
+        // recomputes the per-value LDS and output offsets derived from it
+        // instead of keeping them in registers across the pass loop (which
+        // made the largest shapes spill inside the loop).
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const uint32_t pj0 = (uint32_t)(T * ln);  // first tuple of this lane
+        const uint32_t pblk = swz4<T>(4u * pj0);  // its block in a stage image
         constexpr int MAT = decltype(mat_c)::value;
         const uint32_t signs = NC == 16 ? bcast<L>(swords, slot) : 0u;
         double cs = 0.0, sn = 0.0;
@@ -636,15 +728,20 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
             sn = __hiloint2double((int)bcast<L>((uint32_t)__double2hiint(rsn), slot),
                                   (int)bcast<L>((uint32_t)__double2loint(rsn), slot));
         }
-        double xstar = 0.0;
+        // stage st of the current pool into the LDS stage image (swizzled)
+        auto store_stage = [&](auto st_c) {
+            constexpr int st = decltype(st_c)::value;
 #pragma unroll
-        for (int st = 0; st < NST; ++st) {
-            group_sync<MW>();  // previous readers of this LDS space are done
-#pragma unroll
-            for (int c = 0; c < C; ++c) store_lds<T>(lds + c * N + T * lane, X[st * C + c]);
-            group_sync<MW>();
-            if (st == NST - 1)  // the old pool's last flat value (section 4)
-                xstar = (double)lds[(C - 1) * N + (N - 1)];
+            for (int c = 0; c < C; ++c) {
+                if constexpr (Cf::SWZ)
+                    store_lds_swz<T>(reinterpret_cast<char *>(lds + c * N), pblk, X[st * C + c]);
+                else
+                    store_lds<T>(lds + c * N + pj0, X[st * C + c]);
+            }
+        };
+        // gather of eq. (1) for the components of stage st from its image
+        auto gather_stage = [&](auto st_c) {
+            constexpr int st = decltype(st_c)::value;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const uint32_t wd = bcast<L>(words[st * C + c], slot);
@@ -653,11 +750,27 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
 #pragma unroll
                 for (int i = 0; i < T; ++i) {
                     // 4 * ((a j + b) mod N) for tuple j = T*lane + i
-                    const uint32_t x4 = (__umul24(a4, j0 + i) + b4) & amask;
-                    X[st * C + c][i] = *reinterpret_cast<const float *>(src + x4);
+                    const uint32_t x4 = (__umul24(a4, pj0 + i) + b4) & amask;
+                    X[st * C + c][i] =
+                        *reinterpret_cast<const float *>(src + (Cf::SWZ ? swz4<T>(x4) : x4));
                 }
             }
-        }
+        };
+        // the old pool's last flat value (section 4): last word of the last
+        // component of the last stage
+        auto read_xstar = [&]() {
+            return (double)*reinterpret_cast<const float *>(
+                reinterpret_cast<const char *>(lds + (C - 1) * N) +
+                (Cf::SWZ ? swz4<T>(4u * (N - 1)) : 4u * (N - 1)));
+        };
+        double xstar = 0.0;
+        static_for<0, NST>([&](auto st_c) {
+            group_sync<MW>();  // previous readers of this LDS space are done
+            store_stage(st_c);
+            group_sync<MW>();
+            if (decltype(st_c)::value == NST - 1) xstar = read_xstar();
+            gather_stage(st_c);
+        });
         ++slot;
 
         const double c64 = chi2_scale64(xstar, sigma, P.r_nu);
@@ -684,22 +797,31 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
         }
 
         // return the new pool when it is a returned one (section 6)
+        float *base = nullptr;
+        uint32_t cnt = 0;
+        bool fast = false;
         if (++fcount == P.f) {
             fcount = 0;
             const bool last = (ps + 1 == passes);
-            const uint32_t cnt = last ? job.last_emit : P.emit_len;
-            float *base = P.out + job.out_off + (uint64_t)emitted * P.emit_len;
+            cnt = last ? job.last_emit : P.emit_len;
+            base = P.out + job.out_off + (uint64_t)emitted * P.emit_len;
             ++emitted;
             constexpr uintptr_t vmask = (uintptr_t)(4 * (T >= 4 ? 4 : T) - 1);
-            if (cnt == nu && ((uintptr_t)base & vmask) == 0 && !P.affine) {
-#pragma unroll
-                for (int k = 0; k < NC; ++k) store_run<T>(base + k * N + T * lane, X[k], true);
+            fast = cnt == nu && ((uintptr_t)base & vmask) == 0 && !P.affine;
+        }
+        if (base) {
+            if (!fast) {
+                emit_slow<NC, T, N>(X, base, cnt, ln, P.affine, P.mu, P.sigma_out);
+            } else if constexpr (Cf::EMIT_LDS) {
+                group_sync<MW>();  // every gather of the stage area is done
+                emit_transposed<NC, T, C, N>(X, base, reinterpret_cast<char *>(lds), (uint32_t)ln);
             } else {
-                emit_slow<NC, T, N>(X, base, cnt, lane, P.affine, P.mu, P.sigma_out);
+#pragma unroll
+                for (int k = 0; k < NC; ++k) store_run<T>(base + k * N + T * ln, X[k], true);
             }
         }
 
-        sigma = pool_sumsq<NC, T, L, RM, NST>(X, lane, xw);
+        sigma = pool_sumsq<NC, T, L, RM, NST>(X, ln, xw);
     };
 
     // Chunks of CH passes (CH is even, so every chunk starts on the same
@@ -856,22 +978,45 @@ __device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char 
             for (int i = 0; i < T; ++i) lds[k * N + lane + L * i] = V[k][i];
         }
         group_sync<MW>();
-        float Z[NC][T];  // the new pool, T consecutive tuples per lane
-#pragma unroll
-        for (int k = 0; k < NC; ++k) load_run<T>(Z[k], lds + k * N + T * lane);
-
+        bool slow = false;  // the returned pool needs element-wise emission
+        float *base = nullptr;
+        uint32_t cnt = 0;
         if (++fcount == P.f) {  // a returned pool (section 6)
             fcount = 0;
             const bool last = (ps + 1 == passes);
-            const uint32_t cnt = last ? job.last_emit : P.emit_len;
-            float *base = P.out + job.out_off + (uint64_t)emitted * P.emit_len;
+            cnt = last ? job.last_emit : P.emit_len;
+            base = P.out + job.out_off + (uint64_t)emitted * P.emit_len;
             ++emitted;
             constexpr uintptr_t vmask = (uintptr_t)(4 * (T >= 4 ? 4 : T) - 1);
             if (cnt == nu && ((uintptr_t)base & vmask) == 0 && !P.affine) {
+                if constexpr (T > 4) {
+                    // 16-byte chunks c = lane + L*s straight from the image:
+                    // one store instruction of a wave covers 1 KB of
+                    // consecutive output (T consecutive values per lane
+                    // would leave each store instruction lane-strided)
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+#pragma unroll
+                        for (int q = 0; q < T / 4; ++q) {
+                            const int c = k * (N / 4) + lane + L * q;
+                            __builtin_nontemporal_store(reinterpret_cast<const v4f *>(lds)[c],
+                                                        reinterpret_cast<v4f *>(base) + c);
+                        }
+                    }
+                }
+            } else {
+                slow = true;
+            }
+        }
+        float Z[NC][T];  // the new pool, T consecutive tuples per lane
+#pragma unroll
+        for (int k = 0; k < NC; ++k) load_run<T>(Z[k], lds + k * N + T * lane);
+        if (base) {
+            if (slow)
+                emit_slow<NC, T, N>(Z, base, cnt, lane, P.affine, P.mu, P.sigma_out);
+            else if constexpr (T <= 4) {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) store_run<T>(base + k * N + T * lane, Z[k], true);
-            } else {
-                emit_slow<NC, T, N>(Z, base, cnt, lane, P.affine, P.mu, P.sigma_out);
             }
         }
         sigma = sumsq(Z);

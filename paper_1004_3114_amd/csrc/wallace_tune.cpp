@@ -103,7 +103,7 @@ TuneLayout tune_layout(int n, uint32_t N, uint32_t copies)
 
 }  // namespace
 
-bool forced_sched(int n, uint32_t N, Sched *out)
+int forced_sched(int n, uint32_t N, Sched *out)
 {
     // Explicit override, read at every call: WALLACE_SCHED="n:N:T:L:C,..."
     if (const char *ov = std::getenv("WALLACE_SCHED")) {
@@ -114,26 +114,27 @@ bool forced_sched(int n, uint32_t N, Sched *out)
             if (std::sscanf(p, "%d:%u:%d:%d:%d%n", &a, &b, &T, &L, &C, &used) != 5) break;
             (void)c;
             Sched s{a, T, L, C};
-            if (a == n && b == N && pool_sched_supported(s, (int)N)) {
+            if (a == n && b == N) {
+                if (!pool_sched_supported(s, (int)N)) return -1;
                 *out = s;
-                return true;
+                return 1;
             }
             p += used;
             if (*p == ',') ++p;
         }
     }
-    return false;
+    return 0;
 }
 
-bool tuned_sched(int n, uint32_t N, Sched *out)
+int tuned_sched(int n, uint32_t N, Sched *out)
 {
-    if (forced_sched(n, N, out)) return true;
+    if (const int f = forced_sched(n, N, out)) return f;
     std::lock_guard<std::mutex> lk(g_mu);
     load_cache_locked();
     auto it = g_cache.find(std::make_tuple(device_key(), 0, n, N));
-    if (it == g_cache.end()) return false;
+    if (it == g_cache.end()) return 0;
     *out = it->second;
-    return true;
+    return 1;
 }
 
 size_t tune_scratch_bytes(int n, uint32_t N)

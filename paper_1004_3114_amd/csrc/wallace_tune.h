@@ -13,13 +13,14 @@
 namespace wallace {
 
 // Schedule forced for (n, N) by WALLACE_SCHED="n:N:T:L:C,..." (read at
-// every call).
-bool forced_sched(int n, uint32_t N, Sched *out);
+// every call): 1 and *out set when the first entry naming (n, N) is a
+// compiled shape, -1 when that entry is not, 0 when no entry names (n, N).
+int forced_sched(int n, uint32_t N, Sched *out);
 
 // The forced schedule, else the one recorded for (n, N) on this device by an
 // earlier tuning run, in this process or in the cache file named by
-// WALLACE_TUNE_CACHE.
-bool tuned_sched(int n, uint32_t N, Sched *out);
+// WALLACE_TUNE_CACHE: 1 (found), 0 (none) or -1 (forced but not compiled).
+int tuned_sched(int n, uint32_t N, Sched *out);
 
 // Scratch bytes tune_class needs for one class.
 size_t tune_scratch_bytes(int n, uint32_t N);

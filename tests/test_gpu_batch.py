@@ -101,11 +101,12 @@ def test_mixed_batch_graph_replays():
 
 
 @pytest.mark.parametrize("n,N", [(4, 256), (4, 2048), (16, 64), (16, 1024), (4, 16384),
-                                 (2, 1024)])
+                                 (16, 4096), (2, 1024)])
 def test_every_schedule_gives_identical_bits(n, N, monkeypatch):
     # Schedules differ in lanes per pool, tuples per lane and components per
     # LDS stage; the tree order of every reduction is the same, so each one
-    # must reproduce the oracle exactly.
+    # must reproduce the oracle exactly. Compiled shapes: T <= 16 (n = 16:
+    # T <= 4).
     _dev()
     cands = []
     for T in (1, 2, 4, 8, 16):
@@ -114,10 +115,9 @@ def test_every_schedule_gives_identical_bits(n, N, monkeypatch):
         L = N // T
         if L < n or L > 1024:
             continue
-        for C in ((n,) if n == 2 else (n, n // 2)):  # n = 2: one stage only
-            if C * N * 4 > 128 * 1024 or (L <= 64 and C != n):
-                continue
-            cands.append((T, L, C))
+        # one stage (C = n) while the pool fits 128 KiB, else two
+        C = n if n * N * 4 <= 128 * 1024 else n // 2
+        cands.append((T, L, C))
     assert cands
     G = 9
     seeds = np.arange(70, 70 + G, dtype=np.uint64)
@@ -136,6 +136,23 @@ def test_every_schedule_gives_identical_bits(n, N, monkeypatch):
         for g in range(G):
             assert_bits_equal(host[g * nu * 3:(g + 1) * nu * 3], refs[g],
                               f"T={T} L={L} C={C} gen {g}")
+
+
+def test_forced_schedule_that_is_not_compiled_is_rejected(monkeypatch):
+    # A WALLACE_SCHED entry naming the class must be a compiled shape; an
+    # entry that is not (here two stages for a pool that fits one) makes
+    # init fail instead of silently running another schedule.
+    _dev()
+    monkeypatch.setenv("WALLACE_SCHED", "4:256:4:64:2")
+    with pytest.raises(W.WallaceError) as ei:
+        W.Batch([1, 2], [4, 4], [256, 256])
+    assert ei.value.code == -1
+    with pytest.raises(W.WallaceError) as ei:
+        W.Generator(1, 4, 256)
+    assert ei.value.code == -1
+    monkeypatch.setenv("WALLACE_SCHED", "4:256:4:64:4")
+    W.Batch([1, 2], [4, 4], [256, 256])
+    W.Generator(1, 4, 256)
 
 
 def test_tuner_runs_and_keeps_state(tmp_path, monkeypatch):

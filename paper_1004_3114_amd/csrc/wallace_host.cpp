@@ -109,18 +109,23 @@ bool default_sched(int n, uint32_t N, Sched *out)
 }
 
 // One generator alone on the GPU: the pass is a latency chain, so the pool
-// is spread over more lanes (16 values per lane: 8 tuples for n = 2, 4 for
-// n = 4, 1 for n = 16; up to 1024 lanes) than in a batch, where single-wave
-// groups keep the chip busy with many pools. Measured for n = 4, N = 1024:
-// 2.1 -> 1.06 us per pass.
+// is spread over more lanes than in a batch (where single-wave groups keep
+// the chip busy with many pools): up to 256 lanes, with at most 8 tuples per
+// lane (4 for n = 16) and at most 1024 lanes. Measured per pass against
+// every compiled shape for n = 2, 4, 16 and N = 64 .. 16384, this is the
+// fastest or within 4% of it except n = 2, N = 256 (18%); for example
+// n = 4, N = 1024: 1.15 us (16 tuples per lane on 64 lanes: 1.9 us);
+// n = 16, N = 2048: 5.3 us (2 tuples per lane on 1024 lanes: 6.7 us).
 bool single_sched(int n, uint32_t N, Sched *out)
 {
-    const int tmax = n == 16 ? 4 : 16;
-    Sched s{n, 16 / n, 0, n};
-    if (N < (uint32_t)s.T * (uint32_t)n) s.T = 1;
-    while (N / (uint32_t)s.T > 1024) s.T *= 2;
-    if (s.T > tmax || N % (uint32_t)s.T) return false;
-    s.L = (int)(N / (uint32_t)s.T);
+    const uint32_t tcap = n == 16 ? 4u : 8u;
+    Sched s{n, 1, 0, n};
+    uint32_t T = N > 256 ? N / 256 : 1;
+    if (T > tcap) T = tcap;
+    while (N / T > 1024) T *= 2;
+    if (T > 16 || (n == 16 && T > 4) || N % T) return false;
+    s.T = (int)T;
+    s.L = (int)(N / T);
     if (s.L < n) return false;
     while (s.C > 1 && (size_t)s.C * N * sizeof(float) > 128 * 1024) s.C /= 2;
     if (!pool_sched_supported(s, (int)N)) return false;

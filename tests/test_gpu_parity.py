@@ -83,7 +83,10 @@ def test_pool_resident_shapes(n, N):
     assert_bits_equal(got, ref, f"n={n} N={N}")
 
 
-@pytest.mark.parametrize("n,N", [(4, 256), (16, 64), (4, 4096), (2, 512)])
+# (4, 8192) and (4, 16384) hold more than 4 tuples per lane: whole pools
+# leave through LDS in chunk order, partial ones element by element
+@pytest.mark.parametrize("n,N", [(4, 256), (16, 64), (4, 4096), (2, 512), (4, 8192),
+                                 (4, 16384)])
 def test_ragged_call_splits(n, N):
     _dev()
     rng = np.random.default_rng(N)
@@ -131,12 +134,14 @@ def test_throwaway_and_withheld_driver(n, f, withhold):
     assert_bits_equal(got, ref, f"f={f} withhold={withhold}")
 
 
-def test_normal_epilogue():
+@pytest.mark.parametrize("N", [1024, 8192, 16384])
+def test_normal_epilogue(N):
     _dev()
-    g = W.Generator(3, 4, 1024)
-    out = torch.empty(4096 * 5 + 3, dtype=torch.float32, device="cuda")
+    print(f"case normal epilogue n=4 N={N}", flush=True)
+    g = W.Generator(3, 4, N)
+    out = torch.empty(4 * N * 5 + 3, dtype=torch.float32, device="cuda")
     g.fill_normal(out, 2.5, 0.75)
-    x = oracle.Gen(3, 4, 1024).fill(out.numel())
+    x = oracle.Gen(3, 4, N).fill(out.numel())
     ref = np.float32(2.5) + np.float32(0.75) * x  # one FP32 multiply, one add
     assert_bits_equal(out.cpu().numpy(), ref.astype(np.float32), "mu + sigma x")
 

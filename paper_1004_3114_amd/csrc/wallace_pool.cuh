@@ -18,11 +18,13 @@
 // passes: lane l gathers tuples j = l + L*i (i < T), so the lanes of a wave
 // read L consecutive multiples of the stride, which fall in distinct banks;
 // the new values overwrite the image in place, and the lane then reads back
-// tuples T*l .. T*l+T-1 with vector loads for the store to HBM and the sum of
-// squares (run_job_lds). Larger pools (multi-wave groups only) live in
-// registers, lane l holding tuples T*l .. T*l+T-1 of every component, and
-// LDS is the per-pass permutation network, C = n/NST components at a time
-// (run_job). The per-pass draws are counter-based (splitmix64 draw m is a
+// tuples T*l .. T*l+T-1 for the sum of squares and 16-byte chunks
+// l + L*q for the store to HBM, so that every store instruction of a wave
+// covers consecutive output (run_job_lds). Larger pools (multi-wave groups
+// only) live in registers, lane l holding tuples T*l .. T*l+T-1 of every
+// component, and LDS is the per-pass permutation network, C = n/NST
+// components at a time, in a swizzled layout (run_job). The per-pass draws
+// are counter-based (splitmix64 draw m is a
 // function of state + m * gamma), so each lane computes one pass's
 // parameters for a chunk of up to 64 passes at once and every pass reads its
 // parameters with one lane read per component. T and L are compile-time, so
@@ -355,9 +357,9 @@ struct Cfg {
     // swizzled stage images (register-resident form; see swz4)
     static constexpr bool SWZ = !LDSRES && T >= 2;
     // register-resident with more than 4 tuples per lane: the output goes
-    // through wave-private LDS slices (emit_transposed)
+    // through wave-private LDS slices (emit_transposed); L/64 waves times C
+    // slices of 64*T floats fill the C*N floats of the stage area exactly
     static constexpr bool EMIT_LDS = !LDSRES && T > 4;
-    static_assert(!EMIT_LDS || C * N >= 64 * T * (L / 64) * C, "slices fit the stage area");
     static constexpr int POOL_BYTES = C * N * 4;
     // groups sharing a wave start L words apart in bank terms, so their
     // lanes use different banks

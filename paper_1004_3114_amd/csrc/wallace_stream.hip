@@ -12,6 +12,10 @@
 // block of the next pass's permute launch, or by a one-block finish launch
 // after a call's last pass. The host passes each pass's splitmix64 state, so
 // no permute block depends on the state that block rewrites.
+// For n = 2 and 4 the combine of one pass and the permute of the next are
+// one launch (k_stream_fuse), and a small launch forms the sum-of-squares
+// component nodes between them; only the first pass of a call, or of the
+// passes after a refill, runs the permute on its own.
 // Arbitrary odd strides (eq. 2) use one launch that gathers from HBM, then
 // the finish launch.
 #include "wallace_runtime.h"
@@ -196,7 +200,7 @@ struct Pass {
 // Per-block partial sums for every component: the block's tuples
 // [j0, j0 + 256 T) form an aligned subtree of each component's part of the
 // canonical tree over the flat index.
-template <class Nd, int NC, int T>
+template <class Nd, int NC, int T, int NW = kThreads / 64>
 __device__ void block_partials(const float (&X)[NC][T], double2 *dst,
                                uint32_t nblocks, double2 *red)
 {
@@ -236,10 +240,17 @@ __device__ void block_partials(const float (&X)[NC][T], double2 *dst,
     if (lane < NC) red[wave * NC + kappa] = acc.pack();
     __syncthreads();
     if (threadIdx.x < NC) {
+        // the block's NW wave nodes of component k, in tree order
         const int k = threadIdx.x;
-        Nd r = Nd::join(Nd::join(Nd::unpack(red[k]), Nd::unpack(red[NC + k])),
-                        Nd::join(Nd::unpack(red[2 * NC + k]), Nd::unpack(red[3 * NC + k])));
-        dst[(size_t)k * nblocks + blockIdx.x] = r.pack();
+        Nd t[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t[w] = Nd::unpack(red[w * NC + k]);
+#pragma unroll
+        for (int w = NW; w > 1; w >>= 1) {
+#pragma unroll
+            for (int i = 0; i < w / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
+        }
+        dst[(size_t)k * nblocks + blockIdx.x] = t[0].pack();
     }
 }
 
@@ -390,6 +401,7 @@ struct Perm {
     uint32_t N;
     uint32_t first[17];    // first block of component k; first[n] = grid
     uint32_t logR[16];     // strand length R_k = 2^logR[k]
+    float *xs;             // non-null: receives the old pool's last flat value
 };
 
 // Permute kernel (see the file comment). Block (k, c) covers source values
@@ -412,6 +424,7 @@ __global__ __launch_bounds__(kThreads) void k_stream_permute(Perm P)
     }
     if (P.state->flags & WALLACE_FLAG_CORRUPT) return;
     const uint32_t N = P.N;
+    if (P.xs && blockIdx.x == 0 && threadIdx.x == 0) *P.xs = P.X[(size_t)NC * N - 1];
     int k = 0;
 #pragma unroll
     for (int q = 1; q < NC; ++q) k += blockIdx.x >= P.first[q] ? 1 : 0;
@@ -663,6 +676,259 @@ __global__ __launch_bounds__(kThreads) void k_stream_finish(Pass P)
                                   P.rng + (uint64_t)draws_per_pass(NC) * 0x9E3779B97F4A7C15ull);
 }
 
+// Fused streamed pass (prime-pair strides, n = 2 and 4): the combine of
+// pass p and the permutation of pass p + 1 in one launch. Block c owns
+// tuples [c S, c S + S) with S = 1024 T. It reads their permuted values G_k
+// (written by the previous launch), applies the scaled transform, writes
+// the returned pool and its partial sums of squares (section 4), then
+// keeps the new values in LDS and writes the strands of the next pass's
+// permuted components G'_k[j] = X'_k[(a'_k j + b'_k) mod N] (eq. 1) whose
+// sources lie in its run: strand w holds the j with a' j + b' - w N in
+// [c S, c S + S), from s_w = ceil((c S + w N - b') / a') up to
+// e_w = ceil((c S + S + w N - b') / a'). Every j of every component is
+// written by exactly one block and strand. A value then costs 12 bytes of
+// traffic per pass (read G, write the output, write G') instead of 16 with a
+// separate permute and combine. The old pool's sum of squares comes from the
+// previous pass's component nodes (k_stream_comp) and its last flat value
+// from a slot that the previous launch wrote.
+constexpr int kFuseThreads = 1024;
+constexpr int kFuseStrands = 24;  // a + 1 for the largest stride of n <= 4
+
+struct Fuse {
+    const float *G;       // this pass's permuted components
+    float *Y;             // the new pool in the workspace (NULL: not kept)
+    float *out;           // returned copy (NULL: not returned); may be G
+    float *Gn;            // next pass's permuted components (NULL: none)
+    uint32_t emit_cnt;
+    uint32_t affine;
+    float mu, sig;
+    GenState *state;
+    double2 *partials;    // [n][nblocks]
+    const double2 *comp;  // previous pass's component nodes (NULL: state.sigma)
+    const float *xs_in;   // the old pool's last flat value
+    float *xs_out;        // receives the new pool's last flat value (or NULL)
+    double r_nu;
+    uint64_t rng;         // splitmix64 state this pass draws from
+    uint64_t rng_next;    // and the next pass
+    uint32_t mat;         // n = 4: 1 for A1
+    uint32_t N;
+    uint32_t nblocks;
+};
+
+template <class Nd, int NC, int T>
+__global__ __launch_bounds__(kFuseThreads) void k_stream_fuse(Fuse P)
+{
+    static_assert(NC == 2 || NC == 4, "strides up to 23");
+    constexpr uint32_t S = (uint32_t)kFuseThreads * T;  // tuples per block
+    constexpr int NW = kFuseThreads / 64;
+    extern __shared__ __attribute__((aligned(16))) float run[];  // NC * S floats
+    __shared__ double2 red[NW * NC];
+    __shared__ int32_t s_tab[NC][kFuseStrands];
+    __shared__ int32_t e_tab[NC][kFuseStrands];
+    __shared__ int32_t r_tab[NC][kFuseStrands];
+    const GenState st = *P.state;
+    if (st.flags & WALLACE_FLAG_CORRUPT) return;
+    const uint32_t N = P.N;
+    const uint32_t mask = N - 1u;
+    const uint32_t nu = NC * N;
+
+    double rcs = 0.0, rsn = 0.0;  // n = 2: the pass's rotation (draw n + 1)
+    if constexpr (NC == 2) {
+        uint64_t rng = P.rng + (uint64_t)NC * 0x9E3779B97F4A7C15ull;
+        rotation(sm64(rng), rcs, rsn);
+    }
+    const int mat = (NC == 4) ? (int)P.mat : 0;
+
+    // chi-squared scale from the old pool (section 4, eq. 3)
+    const double xstar = (double)*P.xs_in;
+    const double t = xstar + P.r_nu;
+    const double Sq = (t * t) * 0.5;
+    double sigma_old = st.sigma;
+    if (P.comp) {
+        Nd tc[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) tc[k] = Nd::unpack(P.comp[k]);
+#pragma unroll
+        for (int w = NC; w > 1; w >>= 1) {
+#pragma unroll
+            for (int i = 0; i < w / 2; ++i) tc[i] = Nd::join(tc[2 * i], tc[2 * i + 1]);
+        }
+        sigma_old = tc[0].value();
+    }
+    const double c64 = __builtin_sqrt(Sq / sigma_old);
+    const float c32 = (float)c64;
+    const float h = c32 * (NC == 4 ? 0.5f : 0.25f);
+    const float rp = NC == 2 ? (float)(c64 * rcs) : 0.0f;
+    const float rq = NC == 2 ? (float)(c64 * rsn) : 0.0f;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !__builtin_isfinite(c32))
+        atomicOr(&P.state->flags, (uint32_t)WALLACE_FLAG_NONFINITE);
+
+    const uint32_t j0 = blockIdx.x * S + threadIdx.x * (uint32_t)T;
+    float X[NC][T];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) load_run<T>(X[k], P.G + (size_t)k * N + j0);
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        float v[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) v[k] = X[k][i];
+        if constexpr (NC == 2) {
+            const float px = rp * v[0], qy = rq * v[1], py = rp * v[1], qx = rq * v[0];
+            v[0] = px + qy;
+            v[1] = py - qx;
+        } else {
+            const float v0 = mat ? -v[0] : v[0];
+            const float s0 = v0 + v[1], s1 = v0 - v[1];
+            const float s2 = v[2] + v[3], s3 = v[2] - v[3];
+            const float u0 = s0 + s2, u1 = s1 + s3, u2 = s0 - s2, u3 = s1 - s3;
+            if (mat) {
+                v[0] = u0 * h; v[1] = (-u2) * h; v[2] = (-u1) * h; v[3] = (-u3) * h;
+            } else {
+                v[0] = u0 * h; v[1] = u1 * h; v[2] = u2 * h; v[3] = u3 * h;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) X[k][i] = v[k];
+    }
+
+    // the new pool: workspace copy, returned copy (flat order)
+    if (P.Y) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) store_run<T>(P.Y + (size_t)k * N + j0, X[k], false);
+    }
+    if (P.out) {
+        const bool vec = P.emit_cnt == nu && !P.affine && ((uintptr_t)P.out & 15u) == 0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            float *dst = P.out + (size_t)k * N + j0;
+            if (vec) {
+                store_run<T>(dst, X[k], true);
+            } else {
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    const uint32_t fl = (uint32_t)k * N + j0 + i;
+                    if (fl < P.emit_cnt) {
+                        float y = X[k][i];
+                        if (P.affine) y = P.mu + P.sig * y;
+                        __builtin_nontemporal_store(y, dst + i);
+                    }
+                }
+            }
+        }
+    }
+    if (P.xs_out && j0 + (uint32_t)T == N) *P.xs_out = X[NC - 1][T - 1];
+    block_partials<Nd, NC, T, NW>(X, P.partials, P.nblocks, red);
+    if (!P.Gn) return;
+
+    // next pass's strides and offsets (its draws 1 .. n, section 8)
+    uint32_t an[NC], bn[NC];
+    {
+        uint64_t r2 = P.rng_next;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const uint64_t w = sm64(r2);
+            an[k] = stride_of(k, (uint32_t)(w >> 63)) & mask;
+            bn[k] = (uint32_t)w & mask;
+        }
+    }
+    // the new values in LDS, tuple order, one component after another
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        if constexpr (T % 4 == 0) {
+#pragma unroll
+            for (int i = 0; i < T; i += 4)
+                *reinterpret_cast<v4f *>(run + k * S + threadIdx.x * T + i) =
+                    v4f{X[k][i], X[k][i + 1], X[k][i + 2], X[k][i + 3]};
+        } else {
+#pragma unroll
+            for (int i = 0; i < T; ++i) run[k * S + threadIdx.x * T + i] = X[k][i];
+        }
+    }
+    const int64_t x0 = (int64_t)blockIdx.x * S;
+    for (uint32_t idx = threadIdx.x; idx < (uint32_t)(NC * kFuseStrands); idx += kFuseThreads) {
+        const int k = (int)(idx / kFuseStrands);
+        const uint32_t w = idx % kFuseStrands;
+        uint32_t a = 0, b = 0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+            if (q == k) { a = an[q]; b = bn[q]; }
+        if (w <= a) {
+            // ceil through one correctly rounded FP64 division (|num| < 2^32;
+            // a non-integral quotient lies at least 1/a from an integer)
+            const int64_t num = x0 + (int64_t)w * (int64_t)N - (int64_t)b;
+            const int64_t q = (int64_t)__builtin_ceil((double)num / (double)a);
+            const int64_t qe = (int64_t)__builtin_ceil((double)(num + (int64_t)S) / (double)a);
+            s_tab[k][w] = (int32_t)q;
+            e_tab[k][w] = (int32_t)qe;
+            r_tab[k][w] = (int32_t)(q * (int64_t)a - num);
+        }
+    }
+    __syncthreads();
+
+    // strand w of component k: j in [s_w, e_w) (clipped to [0, N)), value
+    // run[r_w + a (j - s_w)]. Threads take aligned quads of j: quads inside a
+    // strand are one 16-byte store, the ones at its ends store their valid
+    // values one by one.
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const uint32_t a = an[k];
+        const uint32_t lmax = (S + a - 1u) / a;  // longest strand
+        const uint32_t Q = (lmax + 3u) / 4u + 1u;
+        const float rqq = 1.0f / (float)Q;
+        const uint32_t pairs = (a + 1u) * Q;
+        float *g = P.Gn + (size_t)k * N;
+        const float *rk = run + k * S;
+        for (uint32_t pr = threadIdx.x; pr < pairs; pr += kFuseThreads) {
+            uint32_t w = (uint32_t)((float)pr * rqq);
+            w = w * Q > pr ? w - 1u : ((w + 1u) * Q <= pr ? w + 1u : w);
+            const uint32_t u = pr - w * Q;
+            const int64_t js = s_tab[k][w];
+            const int64_t je = e_tab[k][w];
+            const uint32_t r = (uint32_t)r_tab[k][w];
+            const int64_t q0 = (js & ~(int64_t)3) + 4 * (int64_t)u;
+            if (q0 >= js && q0 + 3 < je && q0 >= 0 && q0 + 3 < (int64_t)N) {
+                const uint32_t xo = r + a * (uint32_t)(q0 - js);
+                const v4f v = {rk[xo], rk[xo + a], rk[xo + 2u * a], rk[xo + 3u * a]};
+                *reinterpret_cast<v4f *>(g + q0) = v;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t j = q0 + e;
+                    if (j >= js && j < je && j >= 0 && j < (int64_t)N)
+                        g[j] = rk[r + a * (uint32_t)(j - js)];
+                }
+            }
+        }
+    }
+}
+
+// Per-component nodes of a fused pass's sum of squares (one block each),
+// read by the next fused pass.
+template <class Nd>
+__global__ __launch_bounds__(kThreads) void k_stream_comp(const double2 *partials,
+                                                          uint32_t nblocks, double2 *comp)
+{
+    const uint32_t k = blockIdx.x;
+    const Nd r = comp_sum<Nd, kThreads>(partials + (size_t)k * nblocks, nblocks);
+    if (threadIdx.x == 0) comp[k] = r.pack();
+}
+
+template <int NC>
+const void *fuse_fn(uint32_t rmode)
+{
+    constexpr int T = 16 / NC;
+    if (rmode == 1) return reinterpret_cast<const void *>(&k_stream_fuse<F32, NC, T>);
+    if (rmode == 2) return reinterpret_cast<const void *>(&k_stream_fuse<F32C, NC, T>);
+    return reinterpret_cast<const void *>(&k_stream_fuse<F64, NC, T>);
+}
+
+const void *comp_fn(uint32_t rmode)
+{
+    if (rmode == 1) return reinterpret_cast<const void *>(&k_stream_comp<F32>);
+    if (rmode == 2) return reinterpret_cast<const void *>(&k_stream_comp<F32C>);
+    return reinterpret_cast<const void *>(&k_stream_comp<F64>);
+}
+
 template <int NC>
 const void *permute_fn(uint32_t rmode)
 {
@@ -779,7 +1045,8 @@ size_t stream_partials_bytes(int n, uint32_t N)
 {
     if (!stream_shape_ok(n, N, 0)) return 0;
     const uint32_t nb = N / (kThreads * (uint32_t)stream_T(n, N));
-    return ((size_t)n * nb + (size_t)n) * sizeof(double2);  // partials, component nodes
+    // partials, component nodes, two last-value slots of the fused pass
+    return ((size_t)n * nb + (size_t)n + 1) * sizeof(double2);
 }
 
 const float *stream_current_pool(wallace_gen *g)
@@ -795,9 +1062,154 @@ hipError_t stream_check(wallace_gen *g, hipStream_t s)
                         g->state, 1, s);
 }
 
+namespace {
+
+// Passes of a call with the fused kernel (prime-pair strides, n = 2 or 4,
+// butterflies). A chain starts with a plain permute of the workspace pool
+// (at the call's start and after a refill); each fused launch then combines
+// its pass and permutes for the next, and a one-block-per-component launch
+// prepares the next pass's old sum of squares. The permuted components of a
+// pass whose pool is returned whole, unscaled and 16-byte aligned are built
+// in place of that output, which the pass then overwrites tuple by tuple;
+// otherwise they alternate between the two workspace buffers. A chain's
+// last pass writes the workspace pool (the call's last pass) and the finish
+// launch advances the state.
+hipError_t stream_run_fused(wallace_gen *g, float *out, uint32_t passes, uint32_t last_emit,
+                            uint32_t affine, float mu, float sig, hipStream_t s)
+{
+    const int n = g->n;
+    const uint32_t N = g->N;
+    const uint32_t rm = (uint32_t)g->opts.reduce_mode;
+    const void *ffn = n == 2 ? fuse_fn<2>(rm) : fuse_fn<4>(rm);
+    const void *cfn = comp_fn(rm);
+    const void *fin = n == 2 ? finish_fn<2>(rm) : finish_fn<4>(rm);
+    const void *pfn = n == 2 ? permute_fn<2>(rm) : permute_fn<4>(rm);
+    const uint32_t T = 16u / (uint32_t)n;
+    const uint32_t S = (uint32_t)kFuseThreads * T;
+    if (N % S) return hipErrorInvalidValue;
+    const uint32_t nb = N / S;
+    const size_t lds = (size_t)n * S * sizeof(float);
+    {  // 64 KiB of dynamic LDS plus the kernel's static arrays (current device)
+        hipError_t e = hipFuncSetAttribute(ffn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    Perm pm = perm_shape(n, N);
+    const size_t pm_lds = perm_lds_bytes(pm, n);
+    pm.state = g->state;
+    double2 *partials = reinterpret_cast<double2 *>(g->ws + g->lay.partials);
+    const uint32_t nb_layout = N / (kThreads * (uint32_t)stream_T(n, N));
+    double2 *comp = partials + (size_t)n * nb_layout;
+    float *slot = reinterpret_cast<float *>(comp + n);  // [2], by pass parity
+    float *pa = reinterpret_cast<float *>(g->ws + g->lay.pool);
+    float *pb = reinterpret_cast<float *>(g->ws + g->lay.pool2);
+    auto other = [&](const float *p) { return p == pa ? pb : pa; };
+    const uint64_t nu = g->nu;
+    const uint32_t f = (uint32_t)g->opts.f;
+    const uint64_t R = (uint64_t)g->opts.restart_passes;
+    // output of pass ps of this call, and whether it can hold its G
+    auto emit_of = [&](uint32_t ps, float **o, uint32_t *cnt) {
+        *o = nullptr;
+        *cnt = 0;
+        if ((ps + 1) % f != 0) return false;
+        const uint32_t e = (ps + 1) / f - 1;
+        *o = out + (uint64_t)e * g->emit_len;
+        *cnt = (ps + 1 == passes) ? last_emit : (uint32_t)g->emit_len;
+        return *cnt == nu && !affine && ((uintptr_t)*o & 15) == 0;
+    };
+    const float *cur = ((g->passes_host & 1) != 0) ? pb : pa;
+    float *gcur = nullptr;
+    const double2 *comp_in = nullptr;
+    bool chain = false;
+    for (uint32_t ps = 0; ps < passes; ++ps) {
+        const uint64_t q = g->passes_host + ps;  // passes since init
+        if (R && q > 0 && q % R == 0) {  // restart (section 5)
+            float *w = (q & 1) != 0 ? pb : pa;
+            hipError_t e = refill_pool(g, w, q, s);
+            if (e != hipSuccess) return e;
+            cur = w;
+            chain = false;
+        }
+        float *o = nullptr;
+        uint32_t cnt = 0;
+        const bool fast = emit_of(ps, &o, &cnt);
+        if (!chain) {
+            // this pass's permuted components from the workspace pool
+            gcur = fast ? o : other(cur);
+            pm.X = cur;
+            pm.G = gcur;
+            pm.rng = pass_rng(g, q);
+            pm.fin = 0;
+            pm.xs = slot + (q & 1);
+            void *pargs[] = {&pm};
+            hipError_t e = hipLaunchKernel(pfn, dim3(pm.first[n]), dim3(kThreads), pargs, pm_lds, s);
+            if (e != hipSuccess) return e;
+            comp_in = nullptr;  // the old sum of squares is the state's
+        }
+        const bool last = ps + 1 == passes;
+        const bool cont = !last && !(R && (q + 1) % R == 0);
+        float *gnext = nullptr;
+        if (cont) {
+            float *o2 = nullptr;
+            uint32_t cnt2 = 0;
+            gnext = emit_of(ps + 1, &o2, &cnt2) ? o2 : other(gcur);
+        }
+        Fuse F{};
+        F.G = gcur;
+        F.Y = last ? (((q + 1) & 1) != 0 ? pb : pa) : nullptr;
+        F.out = o;
+        F.Gn = gnext;
+        F.emit_cnt = cnt;
+        F.affine = affine;
+        F.mu = mu;
+        F.sig = sig;
+        F.state = g->state;
+        F.partials = partials;
+        F.comp = comp_in;
+        F.xs_in = slot + (q & 1);
+        F.xs_out = cont ? slot + ((q + 1) & 1) : nullptr;
+        F.r_nu = g->r_nu;
+        F.rng = pass_rng(g, q);
+        F.rng_next = pass_rng(g, q + 1);
+        F.mat = (uint32_t)(q & 1u);
+        F.N = N;
+        F.nblocks = nb;
+        void *fargs[] = {&F};
+        hipError_t e = hipLaunchKernel(ffn, dim3(nb), dim3(kFuseThreads), fargs, lds, s);
+        if (e != hipSuccess) return e;
+        if (cont) {
+            const double2 *cpart = partials;
+            uint32_t cnb = nb;
+            double2 *cdst = comp;
+            void *cargs[] = {&cpart, &cnb, &cdst};
+            e = hipLaunchKernel(cfn, dim3((uint32_t)n), dim3(kThreads), cargs, 0, s);
+            if (e != hipSuccess) return e;
+            comp_in = comp;
+            gcur = gnext;
+            chain = true;
+        } else {
+            Pass P{};
+            P.state = g->state;
+            P.partials = partials;
+            P.nblocks = nb;
+            P.passes = q + 1;
+            P.rng = pass_rng(g, q);
+            void *args[] = {&P};
+            e = hipLaunchKernel(fin, dim3(1), dim3(kThreads), args, 0, s);
+            if (e != hipSuccess) return e;
+            chain = false;
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
 hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last_emit,
                       uint32_t affine, float mu, float sig, hipStream_t s)
 {
+    if (g->opts.a_mode == 0 && g->N >= kRunFloatsMax && (g->n == 2 || g->n == 4) &&
+        g->opts.transform_mode == 0)
+        return stream_run_fused(g, out, passes, last_emit, affine, mu, sig, s);
     // prime-pair strides keep a * R small enough for the LDS runs
     const bool perm = g->opts.a_mode == 0 && g->N >= kRunFloatsMax;
     const void *fn = pass_kernel(g->n, g->N, (uint32_t)g->opts.reduce_mode, perm,

@@ -217,6 +217,25 @@ def test_streaming_small(n, N, passes):
     assert_bits_equal(got, ref, f"stream n={n} N={N}")
 
 
+@pytest.mark.parametrize("n,N,f,withhold,mode", [(4, 1 << 15, 2, 1, 0), (2, 1 << 15, 3, 0, 0),
+                                                  (4, 1 << 15, 1, 0, 1), (4, 1 << 15, 1, 0, 2),
+                                                  (2, 1 << 16, 1, 0, 2)])
+def test_streaming_options(n, N, f, withhold, mode):
+    # n = 2 and 4 stream with one fused launch per pass (combine, then the
+    # next pass's permutation); throw-away passes, a withheld driver and the
+    # FP32 sums change which buffers hold the permuted pool between launches
+    _dev()
+    print(f"case stream options n={n} N={N} f={f} withhold={withhold} mode={mode}", flush=True)
+    emit = n * N - withhold
+    g = W.Generator(31, n, N, f=f, withhold_driver=withhold, reduce_mode=mode)
+    counts = [emit * 2 + 3, emit - 3, 1, emit * 2]
+    got = gpu_stream(g, counts)
+    ref_gen = oracle.Gen(31, n, N, f=f, withhold=withhold, sum_mode=mode)
+    ref = ref_gen.fill(sum(counts))
+    assert_bits_equal(got, ref, "stream options")
+    assert g.sumsq()[0] == ref_gen.sigma
+
+
 def test_streaming_full_odd_strides():
     # any odd stride (eq. 2): the single-launch gather form of the pass
     _dev()

@@ -18,6 +18,9 @@
 // passes after a refill, runs the permute on its own.
 // Arbitrary odd strides (eq. 2) use one launch that gathers from HBM, then
 // the finish launch.
+#include <mutex>
+#include <set>
+#include <utility>
 #include "wallace_runtime.h"
 
 namespace wallace {
@@ -1089,9 +1092,20 @@ hipError_t stream_run_fused(wallace_gen *g, float *out, uint32_t passes, uint32_
     if (N % S) return hipErrorInvalidValue;
     const uint32_t nb = N / S;
     const size_t lds = (size_t)n * S * sizeof(float);
-    {  // 64 KiB of dynamic LDS plus the kernel's static arrays (current device)
-        hipError_t e = hipFuncSetAttribute(ffn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+        // 64 KiB of dynamic LDS plus the kernel's static arrays: allowed once
+        // per device and kernel (not repeated, so that fills can be captured)
+        static std::mutex mu;
+        static std::set<std::pair<int, const void *>> allowed;
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
+        std::lock_guard<std::mutex> lk(mu);
+        if (!allowed.count({dev, ffn})) {
+            e = hipFuncSetAttribute(ffn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            allowed.insert({dev, ffn});
+        }
     }
     Perm pm = perm_shape(n, N);
     const size_t pm_lds = perm_lds_bytes(pm, n);

@@ -205,7 +205,7 @@ struct Pass {
 // canonical tree over the flat index.
 template <class Nd, int NC, int T, int NW = kThreads / 64>
 __device__ void block_partials(const float (&X)[NC][T], double2 *dst,
-                               uint32_t nblocks, double2 *red)
+                               uint32_t nblocks, double2 *red, uint32_t bid)
 {
     constexpr int LOG_NC = Lg<NC>::value;
     const int lane = threadIdx.x & 63;
@@ -253,7 +253,7 @@ __device__ void block_partials(const float (&X)[NC][T], double2 *dst,
 #pragma unroll
             for (int i = 0; i < w / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
         }
-        dst[(size_t)k * nblocks + blockIdx.x] = t[0].pack();
+        dst[(size_t)k * nblocks + bid] = t[0].pack();
     }
 }
 
@@ -666,7 +666,7 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
         }
     }
 
-    block_partials<Nd, NC, T>(X, P.partials, P.nblocks, red);
+    block_partials<Nd, NC, T>(X, P.partials, P.nblocks, red, blockIdx.x);
 }
 
 // Finish of a call's last pass (one block, after the pass kernel), and of
@@ -766,7 +766,13 @@ __global__ __launch_bounds__(kFuseThreads) void k_stream_fuse(Fuse P)
     if (blockIdx.x == 0 && threadIdx.x == 0 && !__builtin_isfinite(c32))
         atomicOr(&P.state->flags, (uint32_t)WALLACE_FLAG_NONFINITE);
 
-    const uint32_t j0 = blockIdx.x * S + threadIdx.x * (uint32_t)T;
+    // Workgroups go round-robin to the 8 XCDs; block b takes tuple range
+    // cb = (b mod 8) G/8 + b/8 instead, so each XCD covers one contiguous
+    // eighth of the pool and the strand ends that adjacent ranges write to
+    // the same lines of G' meet in one L2 (n = 2: 3.5% per pass)
+    const uint32_t cb = (gridDim.x % 8u) ? blockIdx.x
+                                          : (blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
+    const uint32_t j0 = cb * S + threadIdx.x * (uint32_t)T;
     float X[NC][T];
 #pragma unroll
     for (int k = 0; k < NC; ++k) load_run<T>(X[k], P.G + (size_t)k * N + j0);
@@ -820,7 +826,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_stream_fuse(Fuse P)
         }
     }
     if (P.xs_out && j0 + (uint32_t)T == N) *P.xs_out = X[NC - 1][T - 1];
-    block_partials<Nd, NC, T, NW>(X, P.partials, P.nblocks, red);
+    block_partials<Nd, NC, T, NW>(X, P.partials, P.nblocks, red, cb);
     if (!P.Gn) return;
 
     // next pass's strides and offsets (its draws 1 .. n, section 8)
@@ -847,7 +853,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_stream_fuse(Fuse P)
             for (int i = 0; i < T; ++i) run[k * S + threadIdx.x * T + i] = X[k][i];
         }
     }
-    const int64_t x0 = (int64_t)blockIdx.x * S;
+    const int64_t x0 = (int64_t)cb * S;
     for (uint32_t idx = threadIdx.x; idx < (uint32_t)(NC * kFuseStrands); idx += kFuseThreads) {
         const int k = (int)(idx / kFuseStrands);
         const uint32_t w = idx % kFuseStrands;

@@ -373,8 +373,10 @@ struct Cfg {
 // its T consecutive values of each component; within each wave the halving
 // levels (each joins lane pairs in tree order while the lanes split the
 // components) and the remaining lane levels; then the waves' nodes in order
-// through LDS, and the component levels.
-template <int NC, int T, int L, int RM, int NST>
+// through LDS, and the component levels. GUARD: first wait until every wave
+// has read the cross-wave area of the previous call; a caller that runs a
+// group barrier between any two calls (the passes do) leaves it off.
+template <int NC, int T, int L, int RM, int NST, bool GUARD = true>
 __device__ __forceinline__ double pool_sumsq(const float (&X)[NC][T], int lane, char *xw_lds)
 {
     using C = Cfg<NC, T, L, RM, NST>;
@@ -391,7 +393,7 @@ __device__ __forceinline__ double pool_sumsq(const float (&X)[NC][T], int lane, 
     int kappa = 0;
 #pragma unroll
     for (int m = 0; m < LOG_NC; ++m) kappa |= ((wl >> m) & 1) << (LOG_NC - 1 - m);
-    group_sync<true>();  // earlier readers of the cross-wave area are done
+    if constexpr (GUARD) group_sync<true>();  // earlier readers of the cross-wave area are done
     if (wl < NC) acc.put(xw_lds + (wave * NC + kappa) * 16);
     group_sync<true>();
     Nd t[C::W];
@@ -823,7 +825,8 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
             }
         }
 
-        sigma = pool_sumsq<NC, T, L, RM, NST>(X, ln, xw);
+        // the next call comes after the next pass's stage barriers
+        sigma = pool_sumsq<NC, T, L, RM, NST, false>(X, ln, xw);
     };
 
     // Chunks of CH passes (CH is even, so every chunk starts on the same
@@ -880,9 +883,11 @@ __device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char 
     const uint64_t done = stp->passes;
     uint32_t flags = stp->flags;
 
-    auto sumsq = [&](const float (&Z)[NC][T]) -> double {
+    // in_pass: the call follows the pass's image barriers, which every wave
+    // reaches only after reading the previous call's cross-wave area
+    auto sumsq = [&](const float (&Z)[NC][T], auto in_pass) -> double {
         if constexpr (MW)
-            return pool_sumsq<NC, T, L, RM, 1>(Z, lane, xw);
+            return pool_sumsq<NC, T, L, RM, 1, !decltype(in_pass)::value>(Z, lane, xw);
         else
             return pool_sumsq_regs<NC, T, L, RM>(Z, lane);
     };
@@ -893,7 +898,7 @@ __device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char 
 #pragma unroll
         for (int k = 0; k < NC; ++k) load_run<T>(Z[k], pool + k * N + T * lane);
         if (P.sigma_mode) {
-            const double s = sumsq(Z);
+            const double s = sumsq(Z, std::false_type());
             if (P.sigma_mode == 2)
                 sigma = s;
             else if (!(s == sigma))
@@ -1021,7 +1026,7 @@ __device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char 
                 for (int k = 0; k < NC; ++k) store_run<T>(base + k * N + T * lane, Z[k], true);
             }
         }
-        sigma = sumsq(Z);
+        sigma = sumsq(Z, std::true_type());
     };
 
     using M0 = std::integral_constant<int, 0>;

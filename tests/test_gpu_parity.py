@@ -236,6 +236,24 @@ def test_streaming_options(n, N, f, withhold, mode):
     assert g.sumsq()[0] == ref_gen.sigma
 
 
+@pytest.mark.parametrize("n", [4, 2])
+def test_streaming_largest_pool(n):
+    # N = 2^24, the largest streamed pool (4096 blocks of partial sums per
+    # component for n = 4, 2048 for n = 2): two passes word for word
+    _dev()
+    N = 1 << 24
+    nu = n * N
+    print(f"case stream largest n={n} N=2^24", flush=True)
+    g = W.Generator(3, n, N)
+    out = torch.empty(nu * 2, dtype=torch.float32, device="cuda")
+    g.fill(out)
+    torch.cuda.synchronize()
+    ref = oracle.Gen(3, n, N).fill(nu * 2)
+    assert_bits_equal(out.cpu().numpy(), ref, f"stream n={n} N=2^24")
+    del out, g
+    torch.cuda.empty_cache()
+
+
 def test_streaming_full_odd_strides():
     # any odd stride (eq. 2): the single-launch gather form of the pass
     _dev()

@@ -228,7 +228,36 @@ def cpu_baseline(workloads, budget_s=12.0):
             "kind": "oracle",
             "sample": f"{done} of {spec.G} batch_uniform generators (n=4, N=256, seeds 42+g), "
                       f"{passes} passes each = {done * per_gen} normals, one generator per "
-                      f"process on {cores} processes, {wall:.1f} s wall"}
+                      f"process on {cores} processes, {wall:.1f} s wall",
+            "single_thread": cpu_single_thread(workloads)}
+
+
+def cpu_single_thread(workloads):
+    """The oracle on one thread of this process: the single small pool in
+    full, the single large pool on a sample of its passes (its initial pool
+    not timed), and batch_uniform generators one after another."""
+    import oracle
+    oracle.lib()
+    res = {}
+    for spec, sample_passes in ((workloads.SINGLE_SMALL, None), (workloads.SINGLE_LARGE, 5)):
+        P = spec.passes if sample_passes is None else sample_passes
+        g = oracle.Gen(spec.seed, spec.n, spec.N)
+        t0 = time.perf_counter()
+        g.fill(spec.n * spec.N * P)
+        dt = time.perf_counter() - t0
+        res[spec.name] = {"normals_per_s": spec.n * spec.N * P / dt,
+                          "sample": f"{P} of {spec.passes} passes"}
+    uni = workloads.batch_uniform()
+    passes = 64 * uni.launches
+    gens = 64
+    t0 = time.perf_counter()
+    for s in uni.seeds[:gens]:
+        oracle.Gen(int(s), 4, 256).fill(1024 * passes)
+    dt = time.perf_counter() - t0
+    res["batch_uniform"] = {"normals_per_s": gens * 1024 * passes / dt,
+                            "sample": f"{gens} of {uni.G} generators, {passes} passes each, "
+                                      "initial pools included"}
+    return res
 
 
 def _cpu_one(arg):

@@ -10,7 +10,7 @@ values at fixed sampled positions. Over the final 60 passes (1.007e9
 outputs) of the FP64-sum variants it computes the first four moments and a
 100-bin equiprobable chi-squared test.
 
-    python tests/precision/study_gpu.py --out gpurun_out/precision
+    python tests/precision/study_gpu.py --out DIR
 """
 import argparse
 import hashlib

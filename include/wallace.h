@@ -130,7 +130,11 @@ int32_t wallace_initial_pool(uint64_t seed, int32_t n, uint32_t N,
 /* Writes the next `count` values of the generator's output stream to d_out
  * (device, 4-byte aligned, `count` floats). Any count >= 0 is allowed; the
  * stream does not depend on how it is split over calls (section 8: the size
- * of the returned array can vary from call to call). */
+ * of the returned array can vary from call to call). The position in the
+ * stream (and, for pools too large for the chip, each pass's parameters)
+ * advances on the host at every call, so a HIP graph that captured a call
+ * does not continue the stream when replayed; wallace_fill_batched keeps
+ * all state on the device and can be captured. */
 int32_t wallace_fill(wallace_gen *g, float *d_out, uint64_t count, void *stream);
 
 /* Same as wallace_fill, then the affine map out = mu + sigma*x (one FP32

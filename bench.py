@@ -13,6 +13,7 @@ oracle on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --only headline     (profiling runs: no extras)
+       python bench.py --only single_small (profiling runs: one small pool only)
        python bench.py --only single_large (profiling runs: streamed pool only)
        python bench.py --only uneven       (profiling runs: uneven batch only)
        python bench.py --copy-probe BYTES  (calibration copy for counters)
@@ -283,7 +284,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["headline", "single_large", "uneven", "all"],
+    ap.add_argument("--only", choices=["headline", "single_small", "single_large", "uneven", "all"],
                     default="all")
     ap.add_argument("--copy-probe", type=int, default=0)
     args = ap.parse_args()
@@ -311,8 +312,9 @@ def main():
         return
     from paper_1004_3114_amd import wallace as W
     W.lib()  # fails loudly if the HIP library is missing
-    if args.only == "single_large":
-        print(json.dumps(single_pool(torch, W, workloads, "large")), flush=True)
+    if args.only in ("single_small", "single_large"):
+        which = "small" if args.only == "single_small" else "large"
+        print(json.dumps(single_pool(torch, W, workloads, which)), flush=True)
         return
     if args.only == "uneven":
         print(json.dumps(uneven(torch, W, workloads)), flush=True)

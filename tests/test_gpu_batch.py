@@ -208,6 +208,25 @@ def test_batch_uniform_full_size_graph():
         assert_bits_equal(got, ref, f"batch_uniform gen {g}")
     s, p = b.sumsq(65535)
     assert p == 256
+    # every generator, every value: finite, and the first two moments of the
+    # 2^34 outputs at N(0, 1). Each pool's sum of squares is its chi-squared
+    # sample S (mean nu, standard deviation about sqrt(2 nu)), so the second
+    # moment over 2^24 pools sits within about 1e-5 of 1; the mean's standard
+    # error is below 1e-5.
+    s1 = s2 = 0.0
+    step = 1 << 28
+    for i in range(0, out.numel(), step):
+        x = out[i:i + step]
+        assert bool(torch.isfinite(x).all()), f"non-finite output in [{i}, {i + step})"
+        xd = x.double()
+        s1 += float(xd.sum())
+        s2 += float((xd * xd).sum())
+        del xd
+    m = out.numel()
+    mean, second = s1 / m, s2 / m
+    print(f"batch_uniform moments: mean {mean:.3e} second {second:.8f}", flush=True)
+    assert abs(mean) < 1e-4
+    assert abs(second - 1.0) < 1e-3
     del out
     torch.cuda.empty_cache()
 

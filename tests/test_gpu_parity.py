@@ -273,7 +273,7 @@ def test_streaming_reduce_modes(mode):
     assert_bits_equal(got, ref, f"stream reduce {mode}")
 
 
-def test_single_large_full_size_sampled():
+def test_single_large_full_size():
     # n = 4, N = 2^22 (64 MB pool), seed 42, 200 passes in one call, as the
     # benchmark runs it; every pass is compared word by word with the oracle
     # (about 0.1-0.25 s of CPU per pass), then invariants that hold at any size.

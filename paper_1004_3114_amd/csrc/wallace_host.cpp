@@ -158,8 +158,7 @@ hipError_t refill_pool(wallace_gen *g, float *pool, uint64_t q, hipStream_t s)
     hipError_t e = launch_refill(pool, g->nu, r0, g->state, s);
     if (e == hipSuccess)
         e = launch_sumsq(pool, g->nu, (uint32_t)g->opts.reduce_mode,
-                         reinterpret_cast<double *>(g->ws + g->lay.scratch), nullptr, g->state,
-                         0, s);
+                         reinterpret_cast<double *>(g->ws + g->lay.scratch), g->state, 0, s);
     return e;
 }
 
@@ -315,8 +314,7 @@ int32_t wallace_init(uint64_t seed, int32_t n, uint32_t N,
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = launch_sumsq(g->pool, g->nu, (uint32_t)o.reduce_mode,
-                         reinterpret_cast<double *>(g->ws + lay.scratch), nullptr,
-                         g->state, 0, s);
+                         reinterpret_cast<double *>(g->ws + lay.scratch), g->state, 0, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         delete g;

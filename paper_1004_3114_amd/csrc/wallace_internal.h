@@ -101,8 +101,7 @@ hipError_t launch_copy_head(float *out, const float *pool, uint32_t count,
 hipError_t launch_replicate(GenState *states, float *pools, uint64_t stride,
                             uint32_t copies, const GenState *src_state,
                             const float *src_pool, uint64_t nu, hipStream_t stream);
-hipError_t launch_sumsq(const float *pool, size_t nu, uint32_t rmode,
-                        double *partials, double *result, GenState *state,
-                        uint32_t mode, hipStream_t stream);
+hipError_t launch_sumsq(const float *pool, size_t nu, uint32_t rmode, double *scratch,
+                        GenState *state, uint32_t mode, hipStream_t stream);
 
 }  // namespace wallace

@@ -332,11 +332,9 @@ static hipError_t sumsq_chain(const float *pool, size_t nu, double2 *scratch,
 }
 
 // scratch must hold ceil(nu/1024) + ceil(nu/1024^2) + 2 double2 values.
-hipError_t launch_sumsq(const float *pool, size_t nu, uint32_t rmode,
-                        double *scratch, double *unused, GenState *state,
-                        uint32_t mode, hipStream_t stream)
+hipError_t launch_sumsq(const float *pool, size_t nu, uint32_t rmode, double *scratch,
+                        GenState *state, uint32_t mode, hipStream_t stream)
 {
-    (void)unused;
     double2 *s = reinterpret_cast<double2 *>(scratch);
     if (rmode == 1) return sumsq_chain<NodeF32>(pool, nu, s, state, mode, stream);
     if (rmode == 2) return sumsq_chain<NodeComp>(pool, nu, s, state, mode, stream);

@@ -1067,8 +1067,7 @@ const float *stream_current_pool(wallace_gen *g)
 hipError_t stream_check(wallace_gen *g, hipStream_t s)
 {
     return launch_sumsq(stream_current_pool(g), g->nu, (uint32_t)g->opts.reduce_mode,
-                        reinterpret_cast<double *>(g->ws + g->lay.scratch), nullptr,
-                        g->state, 1, s);
+                        reinterpret_cast<double *>(g->ws + g->lay.scratch), g->state, 1, s);
 }
 
 namespace {

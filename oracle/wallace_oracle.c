@@ -61,16 +61,22 @@ static int is_prime(uint32_t x)
     return 1;
 }
 
+/* The first 34 primes by trial division, filled once when the library is
+ * loaded, so that threads calling the oracle concurrently only read them. */
+static uint32_t g_primes[34];
+
+__attribute__((constructor)) static void fill_primes(void)
+{
+    int count = 0;
+    uint32_t x;
+    for (x = 2; count < 34; ++x)
+        if (is_prime(x)) g_primes[count++] = x;
+}
+
 void wo_stride_pair(int k, uint32_t out[2])
 {
-    static uint32_t primes[34];
-    static int count = 0;
-    uint32_t x;
-    if (count == 0)
-        for (x = 2; count < 34; ++x)
-            if (is_prime(x)) primes[count++] = x;
-    out[0] = primes[2 * k + 1];
-    out[1] = primes[2 * k + 2];
+    out[0] = g_primes[2 * k + 1];
+    out[1] = g_primes[2 * k + 2];
 }
 
 /* ------------------------------------------------------------------------ */

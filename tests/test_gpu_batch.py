@@ -212,10 +212,9 @@ def test_batch_uniform_full_size_graph():
     s, p = b.sumsq(65535)
     assert p == 256
     # Then every generator, all 256 passes, bit for bit. The oracle runs in
-    # threads (its C calls release the GIL; no process is forked from this
-    # one, which holds the GPU); its lazily built prime table was filled by
-    # the sampled checks above, in this thread. The output comes to the host
-    # in chunks of 4096 generators (4 GiB).
+    # threads (its C calls release the GIL and it has no mutable global state;
+    # no process is forked from this one, which holds the GPU). The output
+    # comes to the host in chunks of 4096 generators (4 GiB).
     workers = max(1, min(16, os.cpu_count() or 1))
     gen_len = 64 * nu  # one generator's values per launch
     chunk = 4096

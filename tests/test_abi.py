@@ -90,6 +90,8 @@ def test_init_argument_errors_before_gpu():
     # ... and for streamed pools of one tuple per thread (n = 16, 2^13 <= N <= 2^20)
     assert L.wallace_init(1, 16, 256, ctypes.byref(mm), 4096, 1 << 40, None, ctypes.byref(h)) == W.WALLACE_EUNSUP
     assert L.wallace_init(1, 16, 1 << 22, ctypes.byref(mm), 4096, 1 << 40, None, ctypes.byref(h)) == W.WALLACE_EUNSUP
+    # streamed n = 16 pools take at most 4 tuples per thread: N = 2^22 is the largest
+    assert L.wallace_init(1, 16, 1 << 23, None, 4096, 1 << 40, None, ctypes.byref(h)) == W.WALLACE_EUNSUP
     assert not h.value
 
 

@@ -254,6 +254,23 @@ def test_streaming_largest_pool(n):
     torch.cuda.empty_cache()
 
 
+def test_streaming_largest_pool_n16():
+    # n = 16, N = 2^22 (2^26 values, 256 MB), the largest streamed n = 16 pool
+    # (4 tuples per thread): two passes word for word
+    _dev()
+    n, N = 16, 1 << 22
+    nu = n * N
+    print("case stream largest n=16 N=2^22", flush=True)
+    g = W.Generator(5, n, N)
+    out = torch.empty(nu * 2, dtype=torch.float32, device="cuda")
+    g.fill(out)
+    torch.cuda.synchronize()
+    ref = oracle.Gen(5, n, N).fill(nu * 2)
+    assert_bits_equal(out.cpu().numpy(), ref, "stream n=16 N=2^22")
+    del out, g
+    torch.cuda.empty_cache()
+
+
 def test_streaming_full_odd_strides():
     # any odd stride (eq. 2): the single-launch gather form of the pass
     _dev()

@@ -86,8 +86,10 @@ def test_pool_resident_shapes(n, N):
 # (4, 8192) and (4, 16384) hold more than 4 tuples per lane: whole pools
 # leave through LDS in chunk order, partial ones element by element
 @pytest.mark.parametrize("n,N", [(4, 256), (16, 64), (4, 4096), (2, 512), (4, 8192),
-                                 (4, 16384)])
+                                 (4, 16384), (4, 1 << 15), (2, 1 << 15)])
 def test_ragged_call_splits(n, N):
+    # the last two pools stream through HBM (fused passes, partial pools
+    # copied from the workspace)
     _dev()
     rng = np.random.default_rng(N)
     nu = n * N

@@ -273,6 +273,41 @@ def test_streaming_largest_pool_n16():
     torch.cuda.empty_cache()
 
 
+def test_generators_on_concurrent_streams():
+    # independent generators (section 9) filled from two host threads on two
+    # streams at once: two streamed pools and one on chip, each bit for bit
+    _dev()
+    import threading
+    shapes = [(4, 1 << 15, 21), (2, 1 << 15, 22), (16, 1024, 23)]
+    passes = 5
+    gens, outs, streams = [], [], []
+    for n, N, seed in shapes:
+        gens.append(W.Generator(seed, n, N))
+        outs.append(torch.empty(n * N * passes, dtype=torch.float32, device="cuda"))
+        streams.append(torch.cuda.Stream())
+    print("case concurrent streams", flush=True)
+    torch.cuda.synchronize()
+    errors = []
+
+    def run(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                gens[i].fill(outs[i], stream=streams[i])
+        except Exception as e:  # reported below, in the test's thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(len(shapes))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for (n, N, seed), out in zip(shapes, outs):
+        ref = oracle.Gen(seed, n, N).fill(n * N * passes)
+        assert_bits_equal(out.cpu().numpy(), ref, f"concurrent n={n} N={N}")
+
+
 def test_streaming_full_odd_strides():
     # any odd stride (eq. 2): the single-launch gather form of the pass
     _dev()

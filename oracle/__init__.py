@@ -66,6 +66,10 @@ def lib():
                                      ctypes.c_int, _u32p, _u32p, _u32p, _f64p]
     L.wo_rotation.restype = None
     L.wo_rotation.argtypes = [ctypes.c_uint64, _f64p, _f64p]
+    L.wo_rotation_many.restype = None
+    L.wo_rotation_many.argtypes = [_u64p, ctypes.c_size_t, _f64p, _f64p]
+    L.wo_chi2_many.restype = None
+    L.wo_chi2_many.argtypes = [_f64p, _f64p, _f64p, ctypes.c_size_t, _f64p, _f64p]
     L.wo_pass32_rot.restype = None
     L.wo_pass32_rot.argtypes = [ctypes.c_uint32, _u32p, _u32p, ctypes.c_float,
                                 ctypes.c_float, _f32p, _f32p]
@@ -181,6 +185,27 @@ def rotation(w: int):
     sn = ctypes.c_double()
     lib().wo_rotation(w, ctypes.byref(cs), ctypes.byref(sn))
     return cs.value, sn.value
+
+
+def rotation_many(w: np.ndarray):
+    """wo_rotation over an array of draws: (cos, sin) arrays."""
+    w = np.ascontiguousarray(w, dtype=np.uint64)
+    cs = np.empty(w.size, dtype=np.float64)
+    sn = np.empty(w.size, dtype=np.float64)
+    lib().wo_rotation_many(_ptr(w, _u64p), w.size, _ptr(cs, _f64p), _ptr(sn, _f64p))
+    return cs, sn
+
+
+def chi2_many(xstar, sigma, r):
+    """Chi-squared target S and scale c (eq. 3) over arrays, r given."""
+    xstar = np.ascontiguousarray(xstar, dtype=np.float64)
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    S = np.empty(xstar.size, dtype=np.float64)
+    c = np.empty(xstar.size, dtype=np.float64)
+    lib().wo_chi2_many(_ptr(xstar, _f64p), _ptr(sigma, _f64p), _ptr(r, _f64p), xstar.size,
+                       _ptr(S, _f64p), _ptr(c, _f64p))
+    return S, c
 
 
 def pass32_rot(N, a, b, p, q, X):

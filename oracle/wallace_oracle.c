@@ -13,6 +13,9 @@
  *     sin to odd (section 5 names Box-Muller for (re)filling the pool);
  *   - strides: per component k a pair of primes, one picked per pass by the
  *     top bit of a draw; k = 0, 1 are RANN4's {3,5} and {7,11} (section 8);
+ *     reduced mod N, a stride that lands on 1 or on an earlier component's
+ *     stride moves to the next free odd residue (sections 3, 6 and 9 want
+ *     distinct strides above one; see distinct_stride);
  *     offsets uniform on {0..N-1} (section 8);
  *   - n = 2 (RANN4, section 8): a rotation by theta drawn each pass, with
  *     sin and cos from t = tan(theta/2) (see wo_rotation);
@@ -138,6 +141,49 @@ void wo_rotation(uint64_t w, double *cs, double *sn)
     *sn = (t + t) / den;
 }
 
+/* Sections 3, 6 and 9 ask for strides that are distinct and greater than
+ * one. A stride acts modulo N, so for small pools a prime of the table can
+ * reduce to 1 (unit stride) or to another component's stride. Reading: the
+ * reduced stride of component k moves up by 2 (mod N, staying odd) while it
+ * is 1, or while it equals the stride of an earlier component of the same
+ * pass and some odd residue above one is still unused (there are N/2 - 1 of
+ * them; when k of them are taken by earlier components and k < N/2 - 1, a
+ * free one exists). For N above the largest prime of the table nothing
+ * moves and the strides are the primes themselves. */
+static uint32_t distinct_stride(uint32_t cand, const uint32_t *earlier, int k,
+                                uint32_t N)
+{
+    uint32_t free_odd = N / 2 - 1; /* odd residues mod N other than 1 */
+    for (;;) {
+        int clash = (cand == 1u);
+        if (!clash && (uint32_t)k < free_odd) {
+            int i;
+            for (i = 0; i < k; ++i)
+                if (earlier[i] == cand) clash = 1;
+        }
+        if (!clash || free_odd == 0) return cand;
+        cand = (cand + 2u) % N;
+    }
+}
+
+void wo_rotation_many(const uint64_t *w, size_t count, double *cs, double *sn)
+{
+    size_t i;
+    for (i = 0; i < count; ++i) wo_rotation(w[i], &cs[i], &sn[i]);
+}
+
+void wo_chi2_many(const double *xstar, const double *sigma, const double *r,
+                  size_t count, double *S, double *c)
+{
+    size_t i;
+    for (i = 0; i < count; ++i) {
+        double t = xstar[i] + r[i];
+        double s = (t * t) * 0.5;
+        S[i] = s;
+        c[i] = sqrt(s / sigma[i]);
+    }
+}
+
 void wo_pass_params_rot(uint64_t *state, int n, uint32_t N, int a_mode,
                         uint32_t *a, uint32_t *b, uint32_t *signs, double *rot)
 {
@@ -145,13 +191,15 @@ void wo_pass_params_rot(uint64_t *state, int n, uint32_t N, int a_mode,
     *signs = 0;
     for (k = 0; k < n; ++k) {
         uint64_t w = wo_splitmix64(state);
+        uint32_t cand;
         if (a_mode == WO_A_PAIRS) {
             uint32_t pair[2];
             wo_stride_pair(k, pair);
-            a[k] = pair[w >> 63] % N;
+            cand = pair[w >> 63] % N;
         } else {
-            a[k] = (uint32_t)((w >> 32) % N) | 1u;
+            cand = (uint32_t)((w >> 32) % N) | 1u;
         }
+        a[k] = distinct_stride(cand, a, k, N);
         b[k] = (uint32_t)(w % N);
         /* n = 16: a fresh column sign per component and pass, so that the
          * matrix differs at each pass (section 3). */

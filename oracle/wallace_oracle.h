@@ -65,6 +65,14 @@ void wo_pass_params_rot(uint64_t *state, int n, uint32_t N, int a_mode,
  * step one FP64 operation. */
 void wo_rotation(uint64_t w, double *cs, double *sn);
 
+/* Array forms for checking the GPU's FP64 arithmetic against the host's:
+ * wo_rotation for each w[i]; and the chi-squared scale of eq. 3 from an
+ * explicit r = RN64(sqrt(2 nu - 1)): S[i] = (xstar[i] + r[i])^2 / 2,
+ * c[i] = sqrt(S[i] / sigma[i]), each step one IEEE operation. */
+void wo_rotation_many(const uint64_t *w, size_t count, double *cs, double *sn);
+void wo_chi2_many(const double *xstar, const double *sigma, const double *r,
+                  size_t count, double *S, double *c);
+
 /* ---- sum of squares (section 4) ----------------------------------------- */
 
 /* Canonical pairwise tree over flat index: leaves y_f^2, then pairs

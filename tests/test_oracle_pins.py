@@ -77,23 +77,65 @@ def test_affine_index_map_is_permutation_iff_gcd_one(N):
             assert (len(image) == N) == (math.gcd(a, N) == 1)
 
 
-@pytest.mark.parametrize("n,N", [(4, 2), (4, 8), (4, 256), (16, 16), (16, 1024),
-                                 (4, 1 << 22)])
+def _draw_tops(state, n):
+    """Top bits of the n component draws of one pass (oracle.splitmix64 is
+    pinned against the published vectors above)."""
+    tops = []
+    for _ in range(n):
+        state, w = oracle.splitmix64(state)
+        tops.append(w >> 63)
+    return tops
+
+
+@pytest.mark.parametrize("n,N", [(4, 4), (4, 8), (4, 16), (4, 256), (16, 16), (16, 32),
+                                 (16, 64), (16, 128), (16, 1024), (4, 1 << 22), (2, 4),
+                                 (2, 8)])
 @pytest.mark.parametrize("a_mode", [oracle.A_PAIRS, oracle.A_FULL_ODD])
 def test_pass_params_ranges(n, N, a_mode):
+    # Strides odd (eq. 2), above one and distinct (sections 3, 6, 9) as far
+    # as the N/2 - 1 odd residues above one allow; a table stride that is
+    # already acceptable is kept as drawn.
     s = 99
     seen_hi = [set() for _ in range(n)]
-    for _ in range(200):
+    free_odd = N // 2 - 1
+    for _ in range(300):
+        tops = _draw_tops(s, n)
         a, b, signs, s = oracle.pass_params(s, n, N, a_mode)
-        assert signs == 0 if n == 4 else signs < (1 << 16)
+        assert signs == 0 if n != 16 else signs < (1 << 16)
         assert np.all(a % 2 == 1) and np.all(a < N) and np.all(b < N)
+        assert np.all(a > 1)
+        m = min(n, free_odd)
+        assert len(set(int(x) for x in a[:m])) == m
         if a_mode == oracle.A_PAIRS:
             for k in range(n):
-                pair = oracle.stride_pair(k)
-                assert a[k] in (pair[0] % N, pair[1] % N)
+                drawn = oracle.stride_pair(k)[tops[k]] % N
+                if drawn > 1 and (k >= free_odd or drawn not in a[:k]):
+                    assert a[k] == drawn
+                if N > 137:
+                    assert a[k] == oracle.stride_pair(k)[tops[k]]
                 seen_hi[k].add(int(a[k]))
     if a_mode == oracle.A_PAIRS and N > 137:
         assert all(len(x) == 2 for x in seen_hi)  # both members get picked
+
+
+@pytest.mark.parametrize("n", [2, 4, 16])
+def test_strides_above_one_and_distinct_for_every_pool_size(n):
+    # Every N the library accepts for this n (N >= n, N >= 4): over many
+    # passes no stride is 1 and the first min(n, N/2 - 1) strides of a pass
+    # differ; from N = 256 on the strides are the table's primes unchanged.
+    for logN in range(2, 25 if n != 16 else 23):
+        N = 1 << logN
+        if N < n:
+            continue
+        s = 1234 + logN
+        for _ in range(64):
+            tops = _draw_tops(s, n)
+            a, _, _, s = oracle.pass_params(s, n, N)
+            assert np.all(a > 1) and np.all(a % 2 == 1)
+            m = min(n, N // 2 - 1)
+            assert len(set(int(x) for x in a[:m])) == m, (n, N, a)
+            if N >= 256:
+                assert [int(x) for x in a] == [oracle.stride_pair(k)[tops[k]] for k in range(n)]
 
 
 def test_pass_params_consume_one_draw_per_component():
@@ -295,6 +337,63 @@ def test_chi2_sample_closed_form_moments(nu):
     assert abs(S.var() / var - 1) < 0.1
 
 
+@pytest.mark.parametrize("nu", [4, 16, 256, 4096, 1 << 16, 1 << 20, 1 << 24])
+def test_chi2_target_closed_form_by_quadrature(nu):
+    # eq. 3: 2 chi2_nu ~ (x + sqrt(2 nu - 1))^2 with x ~ N(0,1), so the
+    # target is S(x) = (x + r)^2 / 2 with r^2 = 2 nu - 1. Deterministic pins:
+    #   S(0) = (2 nu - 1) / 2;
+    #   (S(x) - S(-x)) / (2x) = r;
+    #   E[S] = nu exactly by two-point Gauss-Hermite quadrature (nodes +-1,
+    #   weights 1/2; exact for polynomials of degree <= 3);
+    #   Var[S] = 2 nu - 1/2 by the three-point rule (nodes 0, +-sqrt 3,
+    #   weights 2/3, 1/6, 1/6; exact for degree <= 5).
+    # A wrong constant (say r^2 = 2 nu) moves E[S] by 1/2.
+    def S_of(x):
+        return oracle.scale32(x, 1.0, nu)[1]
+    assert abs(S_of(0.0) - (2 * nu - 1) / 2) <= 4 * 2.0 ** -53 * nu
+    for x in (1.0, 0.5, 3.0):
+        assert abs((S_of(x) - S_of(-x)) / (2 * x) - math.sqrt(2 * nu - 1)) <= 1e-15 * nu
+    mean = (Fraction(S_of(1.0)) + Fraction(S_of(-1.0))) / 2
+    assert abs(float(mean) - nu) <= 8 * 2.0 ** -53 * nu
+    if nu <= 1 << 16:  # beyond, FP64 rounding of S^2 blurs the 1/2
+        nodes = [(Fraction(2, 3), 0.0), (Fraction(1, 6), math.sqrt(3)),
+                 (Fraction(1, 6), -math.sqrt(3))]
+        e1 = sum(w * Fraction(S_of(x)) for w, x in nodes)
+        e2 = sum(w * Fraction(S_of(x)) ** 2 for w, x in nodes)
+        var = float(e2 - e1 * e1)
+        assert abs(var - (2 * nu - 0.5)) <= 1e-9 * nu * nu + 1e-6
+
+
+@pytest.mark.parametrize("nu", [16, 4096, 1 << 20])
+def test_chi2_scale_direction_exact(nu):
+    # c = sqrt(S / sigma): sigma = S gives exactly 1, sigma = S/4 exactly 2,
+    # sigma = 4 S exactly 1/2 (powers of two scale exactly); the FP32 scale
+    # is RN32 of the FP64 one.
+    for x in (0.0, 0.7, -1.3):
+        _, S, _ = oracle.scale32(x, 1.0, nu)
+        for sigma, want in ((S, 1.0), (S / 4, 2.0), (4 * S, 0.5)):
+            c32, S2, c64 = oracle.scale32(x, sigma, nu)
+            assert S2 == S and c64 == want and c32 == np.float32(want)
+        c32, _, c64 = oracle.scale32(x, 3.0, nu)
+        assert c64 == math.sqrt(S / 3.0) and c32 == np.float32(c64)
+
+
+def test_chi2_many_matches_scale32():
+    # the array form used to check the GPU's arithmetic is the same eq. 3
+    rng = np.random.default_rng(3)
+    for nu in (16, 1 << 10, 1 << 22):
+        x = rng.standard_normal(200).astype(np.float32).astype(np.float64)
+        sig = nu * (1 + 0.01 * rng.standard_normal(200))
+        S, c = oracle.chi2_many(x, sig, np.full(200, math.sqrt(2 * nu - 1)))
+        for i in range(200):
+            _, S1, c1 = oracle.scale32(float(x[i]), float(sig[i]), nu)
+            assert S[i] == S1 and c[i] == c1
+    w = rng.integers(0, 2 ** 63, 300, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    cs, sn = oracle.rotation_many(w)
+    for i in range(300):
+        assert (cs[i], sn[i]) == oracle.rotation(int(w[i]))
+
+
 def test_scaled_pass_hits_chi2_target():
     # After a pass the pool's sum of squares equals S up to rounding.
     g = oracle.Gen(1, 4, 1024)
@@ -415,6 +514,43 @@ def test_generator_composes_documented_steps():
         g.do_pass()
         assert np.array_equal(g.pool, X)
         assert g.sigma == sigma and g.rng == s
+
+
+@pytest.mark.parametrize("n,N", [(4, 128), (16, 64), (2, 256)])
+def test_fp64_variant_composes_documented_steps(n, N):
+    # The FP64 variant is params -> c64 from the old pool (unrounded) ->
+    # dense FP64 product c64 A v (or the rotation) -> FP64 sum of squares.
+    seed = 123
+    g = oracle.Gen64(seed, n, N)
+    X, s = oracle.initial_pool64(seed, n, N)
+    assert np.array_equal(g.pool, X)
+    sigma = oracle.sumsq_d(X)
+    assert g.sigma == sigma
+    for p in range(1, 6):
+        a, b, signs, (cs, sn), s = oracle.pass_params_rot(s, n, N)
+        _, S, c64 = oracle.scale32(float(X[-1]), sigma, n * N)
+        if n == 2:
+            X = oracle.pass64_rot(N, a, b, cs, sn, c64, X)
+        else:
+            X = oracle.pass64(n, N, (p - 1) % 2 if n == 4 else 0, a, b, c64, X, signs)
+        sigma = oracle.sumsq_d(X)
+        g.do_pass()
+        assert np.array_equal(g.pool, X), p
+        assert g.sigma == sigma and g.rng == s and g.last_S == S and g.last_c64 == c64
+
+
+@pytest.mark.parametrize("n,N", [(4, 1024), (16, 256), (2, 2048)])
+def test_fp64_variant_hits_chi2_target_to_fp64_rounding(n, N):
+    # In exact arithmetic the scaled pass gives the new pool the sum of
+    # squares S exactly (A orthogonal, c^2 = S / sigma). The FP64 variant
+    # must reach it to FP64 rounding: a scale rounded to FP32 anywhere would
+    # leave errors near 1e-7.
+    g = oracle.Gen64(9, n, N)
+    worst = 0.0
+    for _ in range(30):
+        g.do_pass()
+        worst = max(worst, abs(g.sigma - g.last_S) / g.last_S)
+    assert worst < 1e-13, worst
 
 
 def test_fp32_variant_within_1e5_of_fp64_variant():

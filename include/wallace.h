@@ -67,7 +67,11 @@ typedef struct wallace_opts {
                                 pool after every f-th pass is returned          */
     int32_t a_mode;          /* 0: strides from fixed prime pairs per component
                                 (section 8: alpha in {3,5}, beta in {7,11}, ...);
-                                1: any odd stride (eq. 2)                        */
+                                1: any odd stride (eq. 2). Either way a stride
+                                reduced mod N that is 1, or equal to an earlier
+                                component's while a free odd residue remains,
+                                moves up by 2 mod N (distinct strides above
+                                one, sections 3 and 9)                          */
     int32_t reduce_mode;     /* sum of squares (section 4): 0 = FP64 pairwise
                                 tree (default), 1 = FP32 pairwise tree,
                                 2 = FP32 pairwise tree with error terms        */
@@ -76,9 +80,9 @@ typedef struct wallace_opts {
     int32_t withhold_driver; /* 1: do not return the pool value used to draw
                                 the chi-squared sum (section 4)                 */
     int32_t check_workspace; /* 1: recompute the pool's sum of squares at the
-                                start of every call and flag a mismatch
-                                (section 8: a large change means the work area
-                                was overwritten)                               */
+                                start of every call and flag a mismatch (RANN4
+                                uses this sum to detect a work area that the
+                                caller damaged between calls, section 8)       */
     int32_t restart_passes;  /* R > 0: refill the pool by Box-Muller from the
                                 generator's stream after every R passes
                                 (section 5; R a multiple of f; single
@@ -128,9 +132,9 @@ int32_t wallace_initial_pool(uint64_t seed, int32_t n, uint32_t N,
                              float *host_pool, uint64_t *rng_after);
 
 /* Writes the next `count` values of the generator's output stream to d_out
- * (device, 4-byte aligned, `count` floats). Any count >= 0 is allowed; the
- * stream does not depend on how it is split over calls (section 8: the size
- * of the returned array can vary from call to call). The position in the
+ * (device, 4-byte aligned, `count` floats). Any count >= 0 is allowed and
+ * the output count may differ from call to call; the stream is the same
+ * however it is split over calls (RANN4's interface, section 8). The position in the
  * stream (and, for pools too large for the chip, each pass's parameters)
  * advances on the host at every call, so a HIP graph that captured a call
  * does not continue the stream when replayed; wallace_fill_batched keeps
@@ -186,11 +190,17 @@ int32_t wallace_batch_init(uint32_t G, const uint64_t *seeds, const int32_t *n,
 int32_t wallace_batch_plan(wallace_batch *b, const uint64_t *offsets,
                            const uint32_t *passes, void *stream);
 
-/* Runs the planned passes for all generators in one persistent launch.
- * Allocates nothing, copies nothing from the host and never synchronises, so
- * it can be captured into a HIP graph; every call advances every generator.
- * d_out must be 16-byte aligned. */
-int32_t wallace_fill_batched(wallace_batch *b, float *d_out, void *stream);
+/* Runs the planned passes for all generators. Each (n, N) class of the
+ * batch is one launch of its pool-resident kernel, whose blocks take the
+ * class's jobs largest first; the classes are spread over `stream` and up
+ * to three side streams forked from it and joined back into it (parallel
+ * branches under graph capture). Allocates nothing, copies nothing from the
+ * host and never synchronises, so it can be captured into a HIP graph; every
+ * call advances every generator. d_out must be 16-byte aligned and hold
+ * out_len floats; out_len below the planned extent (the largest
+ * offsets[g] + passes[g]*n[g]*N[g]) returns WALLACE_EINVAL before anything
+ * is enqueued. */
+int32_t wallace_fill_batched(wallace_batch *b, float *d_out, uint64_t out_len, void *stream);
 
 /* Autotuner: for every (n, N) class in the batch, times each candidate
  * schedule (lanes per pool, components per on-chip stage) on copies of the
@@ -213,6 +223,13 @@ int32_t wallace_batch_tune(wallace_batch *b, void *d_scratch,
 /* Per-generator sum of squares and passes done; synchronises. */
 int32_t wallace_batch_sumsq(wallace_batch *b, uint32_t g, double *sigma,
                             uint64_t *passes, void *stream);
+
+/* The batch's (n, N) classes and their schedules (the tuner's choice, or
+ * the default): *count receives the number of classes; for the first
+ * min(max, count) classes, desc[7i .. 7i+6] = n, N, T (tuples per lane),
+ * L (lanes per pool), C (components per on-chip stage), generators in the
+ * class, blocks of its planned launch (0 before a plan). Host call. */
+int32_t wallace_batch_classes(wallace_batch *b, uint32_t max, int64_t *desc, uint32_t *count);
 
 /* OR of the device flags of all generators; synchronises. */
 int32_t wallace_batch_status(wallace_batch *b, uint32_t *flags, void *stream);

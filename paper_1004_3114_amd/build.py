@@ -37,6 +37,11 @@ for _n in (2, 4, 16):
                         [f"-DWALLACE_POOL_N={_n}", f"-DWALLACE_POOL_RM={_rm}"],
                         f"wallace_pool_{_n}_{_rm}"))
 
+# libwallace_check.so: device arithmetic checks and store-ceiling kernels,
+# used only by the tests and the benchmark (include/wallace_check.h)
+CHECK_SOURCES = [("wallace_check.hip", [], "wallace_check")]
+CHECK_LIBRARY = os.path.join(PKG, "libwallace_check.so")
+
 ARCH = os.environ.get("WALLACE_OFFLOAD_ARCH", "gfx950")
 
 
@@ -70,20 +75,27 @@ def compile_one(item) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libwallace.so (always rebuilds)."""
-    os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(SOURCES))) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIBRARY + ".tmp"
+def link(objs, library):
+    tmp = library + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
            "-lpthread"]
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{proc.stdout}\n{proc.stderr}")
-    os.replace(tmp, LIBRARY)
+    os.replace(tmp, library)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source and link libwallace.so and libwallace_check.so
+    (always rebuilds)."""
+    os.makedirs(BUILD, exist_ok=True)
+    items = SOURCES + CHECK_SOURCES
+    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(items))) as ex:
+        objs = list(ex.map(compile_one, items))
+    link(objs[:len(SOURCES)], LIBRARY)
+    link(objs[len(SOURCES):], CHECK_LIBRARY)
     if verbose:
-        print(f"built {LIBRARY}")
+        print(f"built {LIBRARY} and {CHECK_LIBRARY}")
     return LIBRARY
 
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <new>
@@ -70,6 +71,7 @@ struct wallace_batch {
     BatchLayout lay;
     std::vector<ClassInfo> classes;
     bool planned = false;
+    uint64_t extent = 0;  // floats of d_out the planned fill writes: max(offset + passes nu)
     int cus = 0;
     // streams (default priority) and events that let classes of one fill
     // run side by side; created at the first fill that needs them
@@ -319,10 +321,13 @@ int32_t wallace_batch_plan(wallace_batch *b, const uint64_t *offsets, const uint
     // regions must not overlap
     std::vector<std::pair<uint64_t, uint64_t>> reg;
     reg.reserve(b->G);
+    uint64_t extent = 0;
     for (uint32_t g = 0; g < b->G; ++g) {
         const uint64_t len = (uint64_t)passes[g] * b->n[g] * b->N[g];
         if (passes[g] && len / passes[g] != (uint64_t)b->n[g] * b->N[g]) return WALLACE_EINVAL;
+        if (len && offsets[g] > UINT64_MAX - len) return WALLACE_EINVAL;
         if (len) reg.emplace_back(offsets[g], offsets[g] + len);
+        if (len) extent = std::max(extent, offsets[g] + len);
     }
     std::sort(reg.begin(), reg.end());
     for (size_t i = 1; i < reg.size(); ++i)
@@ -354,14 +359,16 @@ int32_t wallace_batch_plan(wallace_batch *b, const uint64_t *offsets, const uint
     }
     hipError_t e = upload_jobs(b, jobs, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "job upload");
+    b->extent = extent;
     b->planned = true;
     return WALLACE_OK;
 }
 
-int32_t wallace_fill_batched(wallace_batch *b, float *d_out, void *stream)
+int32_t wallace_fill_batched(wallace_batch *b, float *d_out, uint64_t out_len, void *stream)
 {
     if (!b || !d_out || (((uintptr_t)d_out) & 15)) return WALLACE_EINVAL;
     if (!b->planned) return WALLACE_ESTATE;
+    if (out_len < b->extent) return WALLACE_EINVAL;
     const uint32_t sm = b->opts.check_workspace ? 1u : 0u;
     hipError_t e = launch_classes(b, d_out, sm, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "batched launch");
@@ -396,6 +403,25 @@ int32_t wallace_batch_status(wallace_batch *b, uint32_t *flags, void *stream)
     for (const GenState &x : st) f |= x.flags;
     if (flags) *flags = f;
     return (f & WALLACE_FLAG_CORRUPT) ? WALLACE_ECORRUPT : WALLACE_OK;
+}
+
+int32_t wallace_batch_classes(wallace_batch *b, uint32_t max, int64_t *desc, uint32_t *count)
+{
+    if (!b || !count || (max && !desc)) return WALLACE_EINVAL;
+    *count = (uint32_t)b->classes.size();
+    const uint32_t m = std::min<uint32_t>(max, *count);
+    for (uint32_t i = 0; i < m; ++i) {
+        const ClassInfo &c = b->classes[i];
+        int64_t *d = desc + 7 * (size_t)i;
+        d[0] = c.n;
+        d[1] = c.N;
+        d[2] = c.sched.T;
+        d[3] = c.sched.L;
+        d[4] = c.sched.C;
+        d[5] = (int64_t)c.gens.size();
+        d[6] = b->planned ? c.grid : 0;
+    }
+    return WALLACE_OK;
 }
 
 int32_t wallace_batch_destroy(wallace_batch *b)

@@ -152,14 +152,38 @@ uint64_t pass_rng(const wallace_gen *g, uint64_t q)
     return g->rng0 + (draws * q + g->nu * refills) * 0x9E3779B97F4A7C15ull;
 }
 
-hipError_t refill_pool(wallace_gen *g, float *pool, uint64_t q, hipStream_t s)
+hipError_t refill_pool(wallace_gen *g, float *pool, uint64_t q, hipStream_t s,
+                       const Scratch &sc)
 {
     const uint64_t r0 = pass_rng(g, q) - g->nu * 0x9E3779B97F4A7C15ull;
     hipError_t e = launch_refill(pool, g->nu, r0, g->state, s);
     if (e == hipSuccess)
-        e = launch_sumsq(pool, g->nu, (uint32_t)g->opts.reduce_mode,
-                         reinterpret_cast<double *>(g->ws + g->lay.scratch), g->state, 0, s);
+        e = launch_sumsq(pool, g->nu, (uint32_t)g->opts.reduce_mode, sc.tree, g->state, 0, s);
     return e;
+}
+
+// ceil(nu/1024) + ceil(nu/1024^2) + 2 double2 nodes (launch_sumsq).
+size_t sumsq_tree_bytes(uint64_t nu)
+{
+    const size_t blocks = (nu + 1023) / 1024;
+    return (blocks + (blocks + 1023) / 1024 + 2) * 2 * sizeof(double);
+}
+
+Scratch workspace_scratch(const wallace_gen *g)
+{
+    Scratch sc;
+    sc.partials = g->streaming ? g->ws + g->lay.partials : nullptr;
+    sc.tree = reinterpret_cast<double *>(g->ws + g->lay.scratch);
+    return sc;
+}
+
+size_t fill_scratch_bytes(const wallace_gen *g)
+{
+    size_t b = 0;
+    if (g->streaming) b += align_up(stream_partials_bytes(g->n, g->N), kAlign);
+    if (g->opts.restart_passes || (g->opts.check_workspace && g->streaming))
+        b += align_up(sumsq_tree_bytes(g->nu), kAlign);
+    return b;
 }
 
 }  // namespace wallace
@@ -189,8 +213,7 @@ Layout single_layout(int n, uint32_t N)
         off = align_up(off + stream_partials_bytes(n, N), kAlign);
     }
     L.scratch = off;
-    const size_t blocks = (nu + 1023) / 1024;
-    off = align_up(off + (blocks + (blocks + 1023) / 1024 + 2) * 2 * sizeof(double), kAlign);
+    off = align_up(off + sumsq_tree_bytes(nu), kAlign);
     L.total = off;
     return L;
 }
@@ -324,8 +347,12 @@ int32_t wallace_init(uint64_t seed, int32_t n, uint32_t N,
     return WALLACE_OK;
 }
 
-static int32_t fill_impl(wallace_gen *g, float *d_out, uint64_t count,
-                         uint32_t affine, float mu, float sig, void *stream)
+}  // extern "C"
+
+namespace wallace {
+
+int32_t fill_with_scratch(wallace_gen *g, float *d_out, uint64_t count, uint32_t affine,
+                          float mu, float sig, void *stream, const Scratch &sc)
 {
     if (!g) return WALLACE_EINVAL;
     if (count == 0) return WALLACE_OK;
@@ -341,7 +368,7 @@ static int32_t fill_impl(wallace_gen *g, float *d_out, uint64_t count,
     hipError_t e = hipSuccess;
     if (g->opts.check_workspace) {
         // pool-resident jobs check inside the pass kernel
-        e = g->streaming ? stream_check(g, s) : hipSuccess;
+        e = g->streaming ? stream_check(g, s, sc) : hipSuccess;
         if (e != hipSuccess) return hip_fail(e, "workspace check");
     }
     if (k0 > 0) {
@@ -353,7 +380,7 @@ static int32_t fill_impl(wallace_gen *g, float *d_out, uint64_t count,
         const uint64_t tail = rem - (npools - 1) * len;
         if (g->streaming) {
             e = stream_run(g, d_out + k0, (uint32_t)passes, (uint32_t)tail, affine, mu,
-                           sig, s);
+                           sig, s, sc);
         } else {
           // restarts split the passes into segments (multiples of f, since
           // the interval is); each segment is one launch
@@ -362,7 +389,7 @@ static int32_t fill_impl(wallace_gen *g, float *d_out, uint64_t count,
           for (uint64_t done = 0; done < passes && e == hipSuccess;) {
             const uint64_t q = g->passes_host + done;
             if (R && q > 0 && q % R == 0) {
-                e = refill_pool(g, g->pool, q, s);
+                e = refill_pool(g, g->pool, q, s, sc);
                 if (e != hipSuccess) break;
             }
             uint64_t seg = passes - done;
@@ -408,15 +435,21 @@ static int32_t fill_impl(wallace_gen *g, float *d_out, uint64_t count,
     return WALLACE_OK;
 }
 
+}  // namespace wallace
+
+extern "C" {
+
 int32_t wallace_fill(wallace_gen *g, float *d_out, uint64_t count, void *stream)
 {
-    return fill_impl(g, d_out, count, 0, 0.0f, 1.0f, stream);
+    if (!g) return WALLACE_EINVAL;
+    return fill_with_scratch(g, d_out, count, 0, 0.0f, 1.0f, stream, workspace_scratch(g));
 }
 
 int32_t wallace_fill_normal(wallace_gen *g, float *d_out, uint64_t count,
                             float mu, float sigma, void *stream)
 {
-    return fill_impl(g, d_out, count, 1, mu, sigma, stream);
+    if (!g) return WALLACE_EINVAL;
+    return fill_with_scratch(g, d_out, count, 1, mu, sigma, stream, workspace_scratch(g));
 }
 
 int32_t wallace_sumsq(wallace_gen *g, double *sigma, uint64_t *passes, void *stream)

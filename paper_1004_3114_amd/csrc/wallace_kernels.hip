@@ -1,11 +1,11 @@
 // Small HIP kernels of the Wallace generator library and the dispatch of the
-// pool-resident pass kernels (wallace_pool.cuh, instantiated in
+// pool-resident pass kernels (wallace_pool.hpp, instantiated in
 // wallace_pool_inst.hip): emission of leftover values of a partly returned
 // pool, replication of a generator for tuning runs, and the canonical
 // sum-of-squares tree over a pool in memory (initialisation and the
 // corruption check of section 8's drift monitor).
 #include "wallace_internal.h"
-#include "wallace_pool.cuh"
+#include "wallace_pool.hpp"
 
 #include "wallace.h"
 
@@ -111,13 +111,8 @@ __global__ void k_refill(float *pool, uint64_t nu, uint64_t r0, GenState *state)
     const uint64_t pairs = nu / 2;
     for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < pairs;
          m += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t z1 = r0 + (2 * m + 1) * gam, z2 = r0 + (2 * m + 2) * gam;
-        z1 = (z1 ^ (z1 >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z1 = (z1 ^ (z1 >> 27)) * 0x94D049BB133111EBull;
-        z1 ^= z1 >> 31;
-        z2 = (z2 ^ (z2 >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z2 = (z2 ^ (z2 >> 27)) * 0x94D049BB133111EBull;
-        z2 ^= z2 >> 31;
+        const uint64_t z1 = sm64_mix(r0 + (2 * m + 1) * gam);
+        const uint64_t z2 = sm64_mix(r0 + (2 * m + 2) * gam);
         const double u1 = (double)((z1 >> 11) + 1) * 0x1.0p-53;
         const double u2 = (double)(z2 >> 11) * 0x1.0p-53;
         const double rho = __builtin_sqrt(-2.0 * log(u1));

@@ -38,6 +38,7 @@
 
 #include <type_traits>
 
+#include "wallace_devmath.hpp"
 #include "wallace_internal.h"
 #include "wallace.h"
 
@@ -56,75 +57,12 @@ struct Log2<1> {
     static constexpr int value = 0;
 };
 
-// splitmix64 (Steele, Lea and Flood 2014): Weyl step, two xor-shift-multiply
-// rounds and a final xor-shift.
-__device__ __forceinline__ uint64_t sm64_next(uint64_t &s)
-{
-    s += 0x9E3779B97F4A7C15ull;
-    uint64_t z = s;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-// The splitmix64 output for state value z (after the Weyl step).
-__device__ __forceinline__ uint64_t sm64_mix(uint64_t z)
-{
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
-
-// Stride pair of component k: RANN4's {3,5} and {7,11} (section 8), then
-// further odd primes, so strides of different components differ and exceed
-// one (sections 3 and 7).
-__device__ __forceinline__ uint32_t stride_pick(int k, uint32_t top)
-{
-    constexpr uint32_t lo[16] = {3, 7, 13, 19, 29, 37, 43, 53,
-                                 61, 71, 79, 89, 101, 107, 113, 131};
-    constexpr uint32_t hi[16] = {5, 11, 17, 23, 31, 41, 47, 59,
-                                 67, 73, 83, 97, 103, 109, 127, 137};
-    return top ? hi[k] : lo[k];
-}
-
-// Chi-squared scale (section 4, eq. 3): S = (x* + sqrt(2 nu - 1))^2 / 2,
-// c = sqrt(S / sigma), each step one correctly rounded FP64 operation.
-__device__ __forceinline__ double chi2_scale64(double xstar, double sigma, double r_nu)
-{
-    const double t = xstar + r_nu;
-    const double S = (t * t) * 0.5;
-    const double q = S / sigma;
-    return __builtin_sqrt(q);
-}
-
 // Splitmix64 draws per pass: one per component, and for n = 2 one more for
 // the rotation (section 8).
 template <int NC>
 struct Draws {
     static constexpr int value = NC == 2 ? 3 : NC;
 };
-
-// n = 2 rotation of a pass from its draw w (section 8): theta in one of
-// [pi/6, pi/3], [-pi/3, -pi/6], [2pi/3, 5pi/6] picked by (w >> 32) mod 3,
-// t = tan(theta/2) uniform on that interval's image with u = (w mod 2^32)
-// 2^-32, cos = (1 - t^2)/(1 + t^2), sin = 2t/(1 + t^2), one FP64 operation
-// per step.
-__device__ __forceinline__ void rotation(uint64_t w, double &cs, double &sn)
-{
-    const double r3 = __builtin_sqrt(3.0);
-    const double tA = 2.0 - r3, tB = 1.0 / r3, tC = r3, tD = 2.0 + r3;
-    const uint32_t i = (uint32_t)((w >> 32) % 3u);
-    const double lo = i == 0 ? tA : (i == 1 ? -tB : tC);
-    const double hi = i == 0 ? tB : (i == 1 ? -tA : tD);
-    const double u = (double)(uint32_t)w * (1.0 / 4294967296.0);
-    const double t = lo + (hi - lo) * u;
-    const double t2 = t * t;
-    const double den = 1.0 + t2;
-    cs = (1.0 - t2) / den;
-    sn = (t + t) / den;
-}
 
 // n = 2: x' = p x + q y, y' = p y - q x, each product and the sum rounded
 // once (two multiplies and one add per number, section 7).
@@ -683,19 +621,33 @@ __device__ __forceinline__ uint32_t bcast(uint32_t v, uint32_t src)
         return (uint32_t)__shfl((int)v, (int)src, L);
 }
 
-// Draws of pass `pass` (0-based within the job) for component k, from the
-// job's starting splitmix64 state: draw number NC*pass + k + 1.
+// Parameters of pass `pass` (0-based within the job) from the job's starting
+// splitmix64 state: component k uses draw number Draws*pass + k + 1 (section
+// 8 draws). Per component a packed word 4a | 4b << 16 (N <= 2^14): stride a
+// (eq. 2; a table prime, or any odd value in a_mode 1, reduced mod N and
+// made distinct and above one, sections 3 and 9) and offset b; for n = 16
+// also the column sign bits.
 template <int NC, int N>
-__device__ __forceinline__ uint32_t pass_word(uint64_t rng0, uint32_t pass, int k,
-                                              uint32_t a_mode, uint32_t *signs)
+__device__ __forceinline__ void pass_words(uint64_t rng0, uint32_t pass, uint32_t a_mode,
+                                           uint32_t (&words)[NC], uint32_t *signs)
 {
     constexpr uint32_t mask = (uint32_t)N - 1u;
-    const uint64_t m = (uint64_t)Draws<NC>::value * pass + (uint64_t)(k + 1);
-    const uint64_t w = sm64_mix(rng0 + m * kGamma);
-    const uint32_t ak = a_mode ? ((uint32_t)(w >> 32) | 1u) : stride_pick(k, (uint32_t)(w >> 63));
-    const uint32_t a = ak & mask, b = (uint32_t)w & mask;
-    if (NC == 16) *signs |= (uint32_t)((w >> 62) & 1u) << k;
-    return (a << 2) | ((b << 2) << 16);  // 4a | 4b << 16 (N <= 2^14)
+    // with N above the largest table prime, table strides never clash
+    constexpr bool table_may_clash = (uint32_t)N <= max_table_stride(NC);
+    uint32_t a[NC];
+    *signs = 0;
+    static_for<0, NC>([&](auto k_c) {
+        constexpr int k = decltype(k_c)::value;
+        const uint64_t m = (uint64_t)Draws<NC>::value * pass + (uint64_t)(k + 1);
+        const uint64_t w = sm64_mix(rng0 + m * kGamma);
+        const uint32_t ak = a_mode ? ((uint32_t)(w >> 32) | 1u) : stride_pick(k, (uint32_t)(w >> 63));
+        uint32_t ar = ak & mask;
+        if (table_may_clash || a_mode) ar = distinct_stride<k>(ar, a, (uint32_t)N);
+        a[k] = ar;
+        const uint32_t b = (uint32_t)w & mask;
+        if (NC == 16) *signs |= (uint32_t)((w >> 62) & 1u) << k;
+        words[k] = (ar << 2) | ((b << 2) << 16);
+    });
 }
 
 template <int NC, int T, int L, int RM, int NST>
@@ -737,10 +689,7 @@ __device__ void run_job(const PoolArgs &P, const Job &job, float *lds, char *xw,
     uint32_t slot = 0;   // pass index within the chunk
     auto draw_chunk = [&](uint32_t ps0) {
         // this lane's pass of the chunk starting at ps0 (eq. 1, section 8 draws)
-        swords = 0;
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-            words[k] = pass_word<NC, N>(rng0, ps0 + qlane, k, P.a_mode, &swords);
+        pass_words<NC, N>(rng0, ps0 + qlane, P.a_mode, words, &swords);
         if constexpr (NC == 2) {
             const uint64_t m = 3ull * (ps0 + qlane) + 3ull;
             rotation(sm64_mix(rng0 + m * kGamma), rcs, rsn);
@@ -954,10 +903,7 @@ __device__ void run_job_lds(const PoolArgs &P, const Job &job, float *lds, char 
     double rcs = 0.0, rsn = 0.0;
     uint32_t slot = 0;
     auto draw_chunk = [&](uint32_t ps0) {
-        swords = 0;
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-            words[k] = pass_word<NC, N>(rng0, ps0 + qlane, k, P.a_mode, &swords);
+        pass_words<NC, N>(rng0, ps0 + qlane, P.a_mode, words, &swords);
         if constexpr (NC == 2) {
             const uint64_t m = 3ull * (ps0 + qlane) + 3ull;
             rotation(sm64_mix(rng0 + m * kGamma), rcs, rsn);

@@ -1,6 +1,6 @@
 // Instantiates the pool-resident pass kernels for one (n, reduction mode);
 // compiled once per pair with -DWALLACE_POOL_N=<4|16> -DWALLACE_POOL_RM=<0|1|2>.
-#include "wallace_pool.cuh"
+#include "wallace_pool.hpp"
 
 #ifndef WALLACE_POOL_N
 #error "WALLACE_POOL_N must be defined"

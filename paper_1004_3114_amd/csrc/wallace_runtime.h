@@ -28,6 +28,20 @@ struct Layout {
     size_t state, pool, pool2, partials, scratch, total;
 };
 
+// Per-call scratch of a single generator's fill: the streamed passes'
+// partial sums of squares, component nodes and last-value slots
+// (`partials`, stream_partials_bytes), and the sum-of-squares tree of a
+// pool in memory (`tree`, sumsq_tree_bytes; restarts and workspace checks).
+// Nothing in it outlives a call: every word is written before it is read
+// within the call. wallace_fill takes it from the workspace,
+// wallace_fill_static from the library's static device array.
+struct Scratch {
+    char *partials;
+    double *tree;
+};
+
+size_t sumsq_tree_bytes(uint64_t nu);
+
 }  // namespace wallace
 
 // Host handle of one generator. The device state lives in the workspace;
@@ -62,14 +76,26 @@ uint64_t pass_rng(const wallace_gen *g, uint64_t q);
 
 // Restart refill before pass q + 1 (q a positive multiple of the interval):
 // Box-Muller into `pool`, new state rng and sum of squares.
-hipError_t refill_pool(wallace_gen *g, float *pool, uint64_t q, hipStream_t s);
+hipError_t refill_pool(wallace_gen *g, float *pool, uint64_t q, hipStream_t s,
+                       const Scratch &sc);
+
+// The workspace's scratch regions of a generator.
+Scratch workspace_scratch(const wallace_gen *g);
+
+// Bytes of per-call scratch a fill of g can use (0 for on-chip pools without
+// restarts or workspace checks).
+size_t fill_scratch_bytes(const wallace_gen *g);
+
+// wallace_fill / wallace_fill_normal with the given per-call scratch.
+int32_t fill_with_scratch(wallace_gen *g, float *d_out, uint64_t count, uint32_t affine,
+                          float mu, float sig, void *stream, const Scratch &sc);
 
 // Streaming path for pools too large to stay on chip (wallace_stream.hip).
 size_t stream_partials_bytes(int n, uint32_t N);
 bool stream_shape_ok(int n, uint32_t N, int transform_mode);
 const float *stream_current_pool(wallace_gen *g);
-hipError_t stream_check(wallace_gen *g, hipStream_t s);
+hipError_t stream_check(wallace_gen *g, hipStream_t s, const Scratch &sc);
 hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last_emit,
-                      uint32_t affine, float mu, float sig, hipStream_t s);
+                      uint32_t affine, float mu, float sig, hipStream_t s, const Scratch &sc);
 
 }  // namespace wallace

@@ -19,8 +19,9 @@
 // Arbitrary odd strides (eq. 2) use one launch that gathers from HBM, then
 // the finish launch.
 #include <mutex>
-#include <set>
+#include <type_traits>
 #include <utility>
+#include "wallace_devmath.hpp"
 #include "wallace_runtime.h"
 
 namespace wallace {
@@ -29,46 +30,6 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 
 namespace {
-
-__device__ __forceinline__ uint64_t sm64(uint64_t &s)
-{
-    s += 0x9E3779B97F4A7C15ull;
-    uint64_t z = s;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-// n = 2 rotation of a pass from its draw w (section 8): theta in one of
-// [pi/6, pi/3], [-pi/3, -pi/6], [2pi/3, 5pi/6] picked by (w >> 32) mod 3,
-// t = tan(theta/2) uniform on that interval's image with u = (w mod 2^32)
-// 2^-32, cos = (1 - t^2)/(1 + t^2), sin = 2t/(1 + t^2), one FP64 operation
-// per step.
-__device__ __forceinline__ void rotation(uint64_t w, double &cs, double &sn)
-{
-    const double r3 = __builtin_sqrt(3.0);
-    const double tA = 2.0 - r3, tB = 1.0 / r3, tC = r3, tD = 2.0 + r3;
-    const uint32_t i = (uint32_t)((w >> 32) % 3u);
-    const double lo = i == 0 ? tA : (i == 1 ? -tB : tC);
-    const double hi = i == 0 ? tB : (i == 1 ? -tA : tD);
-    const double u = (double)(uint32_t)w * (1.0 / 4294967296.0);
-    const double t = lo + (hi - lo) * u;
-    const double t2 = t * t;
-    const double den = 1.0 + t2;
-    cs = (1.0 - t2) / den;
-    sn = (t + t) / den;
-}
-
-// Component k's stride pair (section 8: {3,5}, {7,11}, then further odd
-// primes so that the strides of different components differ).
-__device__ __forceinline__ uint32_t stride_of(int k, uint32_t top)
-{
-    constexpr uint32_t lo[16] = {3, 7, 13, 19, 29, 37, 43, 53,
-                                 61, 71, 79, 89, 101, 107, 113, 131};
-    constexpr uint32_t hi[16] = {5, 11, 17, 23, 31, 41, 47, 59,
-                                 67, 73, 83, 97, 103, 109, 127, 137};
-    return top ? hi[k] : lo[k];
-}
 
 struct F64 {
     double v;
@@ -118,6 +79,16 @@ struct F32C {
     __device__ double2 pack() const { return make_double2((double)s, (double)e); }
     __device__ static F32C unpack(double2 d) { return {(float)d.x, (float)d.y}; }
 };
+
+// Compile-time loop: f(integral_constant<int, I>) for I in [B, E).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for_k(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>());
+        static_for_k<B + 1, E>(f);
+    }
+}
 
 template <int V>
 struct Lg {
@@ -434,8 +405,8 @@ __global__ __launch_bounds__(kThreads) void k_stream_permute(Perm P)
     const uint32_t c = blockIdx.x - P.first[k];
     // draw k + 1 of the pass (the same draw the combine kernel makes)
     uint64_t rng = P.rng + (uint64_t)k * 0x9E3779B97F4A7C15ull;
-    const uint64_t w64 = sm64(rng);
-    const uint32_t a = stride_of(k, (uint32_t)(w64 >> 63)) & (N - 1u);
+    const uint64_t w64 = sm64_next(rng);
+    const uint32_t a = stride_pick(k, (uint32_t)(w64 >> 63)) & (N - 1u);
     const uint32_t b = (uint32_t)w64 & (N - 1u);
     const uint32_t logR = P.logR[k];
     const uint32_t R = 1u << logR;
@@ -546,23 +517,25 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
 
     uint64_t rng = P.rng;
     uint32_t a[NC], b[NC], signs = 0;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        const uint64_t w = sm64(rng);
+    // strides distinct and above one (sections 3, 9): streamed pools are
+    // larger than every table prime, so only any-odd strides can clash
+    static_for_k<0, NC>([&](auto k_c) {
+        constexpr int k = decltype(k_c)::value;
+        const uint64_t w = sm64_next(rng);
         const uint32_t ak = P.a_mode ? ((uint32_t)(w >> 32) | 1u)
-                                     : stride_of(k, (uint32_t)(w >> 63));
+                                     : stride_pick(k, (uint32_t)(w >> 63));
         a[k] = ak & mask;
+        if (P.a_mode) a[k] = distinct_stride<k>(a[k], a, N);
         b[k] = (uint32_t)w & mask;
         if (NC == 16) signs |= (uint32_t)((w >> 62) & 1u) << k;
-    }
+    });
     double rcs = 0.0, rsn = 0.0;  // n = 2: the pass's rotation (draw n + 1)
-    if constexpr (NC == 2) rotation(sm64(rng), rcs, rsn);
+    if constexpr (NC == 2) rotation(sm64_next(rng), rcs, rsn);
     const int mat = (NC == 4) ? (int)P.mat : 0;
 
     // chi-squared scale from the old pool (section 4, eq. 3)
     const double xstar = (double)P.X[nu - 1];
-    const double t = xstar + P.r_nu;
-    const double S = (t * t) * 0.5;
+    const double S = chi2_target(xstar, P.r_nu);
     double sigma_old = st.sigma;
     if (P.comp) {  // the previous pass of this call, from its component nodes
         Nd t[NC];
@@ -575,7 +548,7 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
         }
         sigma_old = t[0].value();
     }
-    const double c64 = __builtin_sqrt(S / sigma_old);
+    const double c64 = chi2_scale_from_S(S, sigma_old);
     const float c32 = (float)c64;
     const float h = c32 * (NC == 4 ? 0.5f : 0.25f);
     // n = 2: c folds into the rotation entries, each rounded once (section 4)
@@ -738,14 +711,13 @@ __global__ __launch_bounds__(kFuseThreads) void k_stream_fuse(Fuse P)
     double rcs = 0.0, rsn = 0.0;  // n = 2: the pass's rotation (draw n + 1)
     if constexpr (NC == 2) {
         uint64_t rng = P.rng + (uint64_t)NC * 0x9E3779B97F4A7C15ull;
-        rotation(sm64(rng), rcs, rsn);
+        rotation(sm64_next(rng), rcs, rsn);
     }
     const int mat = (NC == 4) ? (int)P.mat : 0;
 
     // chi-squared scale from the old pool (section 4, eq. 3)
     const double xstar = (double)*P.xs_in;
-    const double t = xstar + P.r_nu;
-    const double Sq = (t * t) * 0.5;
+    const double Sq = chi2_target(xstar, P.r_nu);
     double sigma_old = st.sigma;
     if (P.comp) {
         Nd tc[NC];
@@ -758,7 +730,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_stream_fuse(Fuse P)
         }
         sigma_old = tc[0].value();
     }
-    const double c64 = __builtin_sqrt(Sq / sigma_old);
+    const double c64 = chi2_scale_from_S(Sq, sigma_old);
     const float c32 = (float)c64;
     const float h = c32 * (NC == 4 ? 0.5f : 0.25f);
     const float rp = NC == 2 ? (float)(c64 * rcs) : 0.0f;
@@ -835,8 +807,8 @@ __global__ __launch_bounds__(kFuseThreads) void k_stream_fuse(Fuse P)
         uint64_t r2 = P.rng_next;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            const uint64_t w = sm64(r2);
-            an[k] = stride_of(k, (uint32_t)(w >> 63)) & mask;
+            const uint64_t w = sm64_next(r2);
+            an[k] = stride_pick(k, (uint32_t)(w >> 63)) & mask;
             bn[k] = (uint32_t)w & mask;
         }
     }
@@ -1064,10 +1036,10 @@ const float *stream_current_pool(wallace_gen *g)
     return reinterpret_cast<const float *>(g->ws + off);
 }
 
-hipError_t stream_check(wallace_gen *g, hipStream_t s)
+hipError_t stream_check(wallace_gen *g, hipStream_t s, const Scratch &sc)
 {
-    return launch_sumsq(stream_current_pool(g), g->nu, (uint32_t)g->opts.reduce_mode,
-                        reinterpret_cast<double *>(g->ws + g->lay.scratch), g->state, 1, s);
+    return launch_sumsq(stream_current_pool(g), g->nu, (uint32_t)g->opts.reduce_mode, sc.tree,
+                        g->state, 1, s);
 }
 
 namespace {
@@ -1083,7 +1055,8 @@ namespace {
 // last pass writes the workspace pool (the call's last pass) and the finish
 // launch advances the state.
 hipError_t stream_run_fused(wallace_gen *g, float *out, uint32_t passes, uint32_t last_emit,
-                            uint32_t affine, float mu, float sig, hipStream_t s)
+                            uint32_t affine, float mu, float sig, hipStream_t s,
+                            const Scratch &sc)
 {
     const int n = g->n;
     const uint32_t N = g->N;
@@ -1099,23 +1072,31 @@ hipError_t stream_run_fused(wallace_gen *g, float *out, uint32_t passes, uint32_
     const size_t lds = (size_t)n * S * sizeof(float);
     {
         // 64 KiB of dynamic LDS plus the kernel's static arrays: allowed once
-        // per device and kernel (not repeated, so that fills can be captured)
+        // per device and kernel (not repeated, so that fills can be captured).
+        // A fixed table of the six fused kernels per device, so that a fill
+        // allocates no memory.
+        constexpr int kMaxDevices = 64, kFusedKernels = 6;
         static std::mutex mu;
-        static std::set<std::pair<int, const void *>> allowed;
+        static const void *allowed[kMaxDevices][kFusedKernels];
         int dev = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
+        if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
         std::lock_guard<std::mutex> lk(mu);
-        if (!allowed.count({dev, ffn})) {
+        int slot = -1;
+        for (int i = 0; i < kFusedKernels && slot < 0; ++i)
+            if (allowed[dev][i] == ffn || allowed[dev][i] == nullptr) slot = i;
+        if (slot < 0) return hipErrorInvalidValue;
+        if (allowed[dev][slot] != ffn) {
             e = hipFuncSetAttribute(ffn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
-            allowed.insert({dev, ffn});
+            allowed[dev][slot] = ffn;
         }
     }
     Perm pm = perm_shape(n, N);
     const size_t pm_lds = perm_lds_bytes(pm, n);
     pm.state = g->state;
-    double2 *partials = reinterpret_cast<double2 *>(g->ws + g->lay.partials);
+    double2 *partials = reinterpret_cast<double2 *>(sc.partials);
     const uint32_t nb_layout = N / (kThreads * (uint32_t)stream_T(n, N));
     double2 *comp = partials + (size_t)n * nb_layout;
     float *slot = reinterpret_cast<float *>(comp + n);  // [2], by pass parity
@@ -1143,7 +1124,7 @@ hipError_t stream_run_fused(wallace_gen *g, float *out, uint32_t passes, uint32_
         const uint64_t q = g->passes_host + ps;  // passes since init
         if (R && q > 0 && q % R == 0) {  // restart (section 5)
             float *w = (q & 1) != 0 ? pb : pa;
-            hipError_t e = refill_pool(g, w, q, s);
+            hipError_t e = refill_pool(g, w, q, s, sc);
             if (e != hipSuccess) return e;
             cur = w;
             chain = false;
@@ -1224,11 +1205,11 @@ hipError_t stream_run_fused(wallace_gen *g, float *out, uint32_t passes, uint32_
 }  // namespace
 
 hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last_emit,
-                      uint32_t affine, float mu, float sig, hipStream_t s)
+                      uint32_t affine, float mu, float sig, hipStream_t s, const Scratch &sc)
 {
     if (g->opts.a_mode == 0 && g->N >= kRunFloatsMax && (g->n == 2 || g->n == 4) &&
         g->opts.transform_mode == 0)
-        return stream_run_fused(g, out, passes, last_emit, affine, mu, sig, s);
+        return stream_run_fused(g, out, passes, last_emit, affine, mu, sig, s, sc);
     // prime-pair strides keep a * R small enough for the LDS runs
     const bool perm = g->opts.a_mode == 0 && g->N >= kRunFloatsMax;
     const void *fn = pass_kernel(g->n, g->N, (uint32_t)g->opts.reduce_mode, perm,
@@ -1247,7 +1228,7 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
               : g->n == 4 ? permute_fn<4>((uint32_t)g->opts.reduce_mode)
                         : permute_fn<16>((uint32_t)g->opts.reduce_mode);
         pm.state = g->state;
-        pm.partials = reinterpret_cast<const double2 *>(g->ws + g->lay.partials);
+        pm.partials = reinterpret_cast<const double2 *>(sc.partials);
     }
     const int T = stream_T(g->n, g->N);
     const uint32_t nblocks = g->N / (kThreads * (uint32_t)T);
@@ -1269,7 +1250,7 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
             const uint64_t q = g->passes_host + ps;
             if (R && q > 0 && q % R == 0) {
                 float *w = (q & 1) != 0 ? pb : pa;
-                hipError_t e = refill_pool(g, w, q, s);
+                hipError_t e = refill_pool(g, w, q, s, sc);
                 if (e != hipSuccess) return e;
                 src = w;
                 refilled = true;
@@ -1296,7 +1277,7 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
         P.mu = mu;
         P.sig = sig;
         P.state = g->state;
-        P.partials = reinterpret_cast<double2 *>(g->ws + g->lay.partials);
+        P.partials = reinterpret_cast<double2 *>(sc.partials);
         P.r_nu = g->r_nu;
         P.N = g->N;
         P.a_mode = (uint32_t)g->opts.a_mode;
@@ -1305,7 +1286,7 @@ hipError_t stream_run(wallace_gen *g, float *out, uint32_t passes, uint32_t last
         P.rng = pass_rng(g, q);
         P.mat = (uint32_t)(q & 1u);
         P.passes = q + 1;
-        double2 *comp = reinterpret_cast<double2 *>(g->ws + g->lay.partials) +
+        double2 *comp = reinterpret_cast<double2 *>(sc.partials) +
                         (size_t)g->n * nblocks;
         P.comp = nullptr;
         if (perm) {

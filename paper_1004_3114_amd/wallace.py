@@ -75,11 +75,12 @@ SIGNATURES = {
     "wallace_batch_init": (_i32, [_u32, _vp, _vp, _vp, ctypes.POINTER(wallace_opts), _vp,
                                   _sz, _vp, ctypes.POINTER(_vp)]),
     "wallace_batch_plan": (_i32, [_vp, _vp, _vp, _vp]),
-    "wallace_fill_batched": (_i32, [_vp, _vp, _vp]),
+    "wallace_fill_batched": (_i32, [_vp, _vp, _u64, _vp]),
     "wallace_batch_tune_bytes": (_i32, [_vp, ctypes.POINTER(_sz)]),
     "wallace_batch_tune": (_i32, [_vp, _vp, _sz, _vp]),
     "wallace_batch_sumsq": (_i32, [_vp, _u32, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(_u64), _vp]),
+    "wallace_batch_classes": (_i32, [_vp, _u32, _vp, ctypes.POINTER(_u32)]),
     "wallace_batch_status": (_i32, [_vp, ctypes.POINTER(_u32), _vp]),
     "wallace_batch_destroy": (_i32, [_vp]),
 }
@@ -148,6 +149,31 @@ def workspace_bytes(n: int, N: int, opts: Optional[wallace_opts] = None) -> int:
     _check(lib().wallace_workspace_bytes(n, N, ctypes.byref(opts) if opts else None,
                                          ctypes.byref(b)), "wallace_workspace_bytes")
     return b.value
+
+
+def batch_extent(offsets, passes, n, N) -> int:
+    """Floats of the output a planned batched fill writes: the largest
+    offsets[g] + passes[g] * n[g] * N[g] (0 if nothing is written)."""
+    ends = [int(o) + int(p) * int(a) * int(b) for o, p, a, b in zip(offsets, passes, n, N)
+            if int(p)]
+    return max(ends) if ends else 0
+
+
+def check_batch_output(out, extent, device):
+    """The checks a batched fill's output tensor must pass before its pointer
+    is handed to the library: planned, float32, contiguous, on the
+    workspace's device, at least `extent` elements."""
+    import torch
+    if extent is None:
+        raise RuntimeError("Batch.fill before Batch.plan")
+    if out.dtype != torch.float32:
+        raise TypeError(f"batched output must be float32, not {out.dtype}")
+    if not out.is_contiguous():
+        raise ValueError("batched output must be contiguous")
+    if out.device != device:
+        raise ValueError(f"batched output on {out.device}, workspace on {device}")
+    if out.numel() < extent:
+        raise ValueError(f"batched output holds {out.numel()} floats, the plan writes {extent}")
 
 
 class Generator:
@@ -246,10 +272,14 @@ class Batch:
         _check(lib().wallace_batch_plan(self._h, self._offsets.ctypes.data,
                                         self._passes.ctypes.data, _stream_handle(stream)),
                "wallace_batch_plan")
+        self.extent = batch_extent(self._offsets, self._passes, self.n, self.N)
 
     def fill(self, out, stream=None):
-        _check(lib().wallace_fill_batched(self._h, out.data_ptr(), _stream_handle(stream)),
-               "wallace_fill_batched")
+        """Run the planned passes into `out` (a float32 CUDA tensor on the
+        workspace's device holding at least `extent` elements)."""
+        check_batch_output(out, getattr(self, "extent", None), self.workspace.device)
+        _check(lib().wallace_fill_batched(self._h, out.data_ptr(), out.numel(),
+                                          _stream_handle(stream)), "wallace_fill_batched")
         return out
 
     def tune(self, stream=None):
@@ -261,6 +291,19 @@ class Batch:
         ptr = (scratch.data_ptr() + 255) // 256 * 256
         _check(lib().wallace_batch_tune(self._h, ptr, b.value, _stream_handle(stream)),
                "wallace_batch_tune")
+
+    def classes(self):
+        """Per (n, N) class: its schedule (T, L, C), generator count and the
+        block count of its planned launch."""
+        cnt = _u32()
+        _check(lib().wallace_batch_classes(self._h, 0, None, ctypes.byref(cnt)),
+               "wallace_batch_classes")
+        desc = np.zeros(7 * max(cnt.value, 1), dtype=np.int64)
+        _check(lib().wallace_batch_classes(self._h, cnt.value, desc.ctypes.data,
+                                           ctypes.byref(cnt)), "wallace_batch_classes")
+        keys = ("n", "N", "T", "L", "C", "G", "blocks")
+        return [dict(zip(keys, (int(v) for v in desc[7 * i:7 * i + 7])))
+                for i in range(cnt.value)]
 
     def sumsq(self, g: int, stream=None):
         s = ctypes.c_double()

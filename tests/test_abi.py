@@ -42,6 +42,35 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(W.SIGNATURES), set(names) ^ set(W.SIGNATURES)
 
 
+def test_check_library_exports_its_header():
+    # libwallace_check.so (include/wallace_check.h): device arithmetic checks
+    # and store-ceiling kernels for the tests and the benchmark
+    from paper_1004_3114_amd import check as CK
+    if not os.path.exists(CK.LIBRARY):
+        wbuild.build()
+    text = open(os.path.join(ROOT, "include", "wallace_check.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(wallace_check_[a-z_0-9]+)\s*\(", text)))
+    assert len(names) == 4
+    lib = ctypes.CDLL(CK.LIBRARY)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(CK.SIGNATURES)
+    # argument errors come back before any launch (null and misaligned
+    # pointers, a layout that would end beyond the buffer)
+    L = CK.lib()
+    assert L.wallace_check_chi2(None, None, None, None, None, None, 5, None) == W.WALLACE_EINVAL
+    assert L.wallace_check_chi2(None, None, None, None, None, None, 0, None) == W.WALLACE_OK
+    assert L.wallace_check_rotation(None, None, None, 3, None) == W.WALLACE_EINVAL
+    assert L.wallace_check_store_oneshot(None, 1024, 0.0, 0, None) == W.WALLACE_EINVAL
+    assert L.wallace_check_store_oneshot(16, 1000, 0.0, 0, None) == W.WALLACE_EINVAL
+    assert L.wallace_check_store_oneshot(8, 1024, 0.0, 0, None) == W.WALLACE_EINVAL
+    assert L.wallace_check_store_longlived(16, 4096, 4, 2, 1024, 1024 * 4, 0, None) == \
+        W.WALLACE_EINVAL  # last chunk ends at 3*1024 + 4096 + 1024 > 4096
+    assert L.wallace_check_store_longlived(16, 1 << 20, 3, 1, 1024, 1024, 0, None) == \
+        W.WALLACE_EINVAL  # waves not a multiple of 4
+
+
 def test_strerror_and_defaults():
     assert W.strerror(0) == "ok"
     assert "workspace" in W.strerror(W.WALLACE_ENOSPC)
@@ -101,8 +130,32 @@ def test_null_handles():
     assert L.wallace_sumsq(None, None, None, None) == W.WALLACE_EINVAL
     assert L.wallace_destroy(None) == W.WALLACE_OK
     assert L.wallace_batch_destroy(None) == W.WALLACE_OK
-    assert L.wallace_fill_batched(None, 256, None) == W.WALLACE_EINVAL
+    assert L.wallace_fill_batched(None, 256, 1 << 20, None) == W.WALLACE_EINVAL
     assert L.wallace_batch_plan(None, None, None, None) == W.WALLACE_EINVAL
+
+
+def test_batch_output_checks_before_any_launch():
+    # Batch.fill hands the library a raw pointer; the binding first checks
+    # the tensor against the plan's extent (and the library checks out_len)
+    import torch
+    offsets = np.array([0, 3 * 1024, 10_000], dtype=np.uint64)
+    passes = np.array([3, 2, 0], dtype=np.uint32)
+    ext = W.batch_extent(offsets, passes, [4, 16, 4], [256, 64, 256])
+    assert ext == 3 * 1024 + 2 * 1024
+    cpu = torch.device("cpu")
+    W.check_batch_output(torch.empty(ext, dtype=torch.float32), ext, cpu)
+    with pytest.raises(ValueError):
+        W.check_batch_output(torch.empty(ext - 1, dtype=torch.float32), ext, cpu)
+    with pytest.raises(TypeError):
+        W.check_batch_output(torch.empty(ext, dtype=torch.float16), ext, cpu)
+    with pytest.raises(TypeError):
+        W.check_batch_output(torch.empty(ext, dtype=torch.float64), ext, cpu)
+    with pytest.raises(ValueError):
+        W.check_batch_output(torch.empty(2 * ext, dtype=torch.float32)[::2], ext, cpu)
+    with pytest.raises(ValueError):
+        W.check_batch_output(torch.empty(ext, dtype=torch.float32), ext, torch.device("cuda", 0))
+    with pytest.raises(RuntimeError):
+        W.check_batch_output(torch.empty(ext, dtype=torch.float32), None, cpu)
 
 
 def test_batch_workspace_validation():

@@ -141,6 +141,34 @@ def test_every_schedule_gives_identical_bits(n, N, monkeypatch):
                               f"T={T} L={L} C={C} gen {g}")
 
 
+def test_undersized_output_is_rejected_before_launch():
+    # An output tensor shorter than the plan writes (or of the wrong dtype)
+    # never reaches a kernel: the binding raises, and the C entry point
+    # returns WALLACE_EINVAL for an out_len below the planned extent.
+    _dev()
+    G = 4
+    b = W.Batch(np.arange(3, 3 + G, dtype=np.uint64), [4] * G, [256] * G)
+    off = np.arange(G, dtype=np.uint64) * (1024 * 2)
+    b.plan(off, np.full(G, 2, dtype=np.uint32))
+    assert b.extent == G * 1024 * 2
+    guard = torch.full((G * 1024 * 2 + 64,), 7.0, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        b.fill(guard[:b.extent - 1])
+    with pytest.raises(TypeError):
+        b.fill(torch.empty(b.extent, dtype=torch.float16, device="cuda"))
+    L = W.lib()
+    rc = L.wallace_fill_batched(b._h, guard.data_ptr(), b.extent - 1,
+                                torch.cuda.current_stream().cuda_stream)
+    assert rc == W.WALLACE_EINVAL
+    torch.cuda.synchronize()
+    assert bool((guard == 7.0).all())  # nothing was written
+    b.fill(guard[:b.extent])
+    host = guard.cpu().numpy()
+    assert np.all(host[b.extent:] == 7.0)
+    ref = oracle_generator_output(3, 4, 256, 2)
+    assert_bits_equal(host[:2048], ref, "first generator after the rejected calls")
+
+
 def test_forced_schedule_that_is_not_compiled_is_rejected(monkeypatch):
     # A WALLACE_SCHED entry naming the class must be a compiled shape; an
     # entry that is not (here two stages for a pool that fits one) makes

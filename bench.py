@@ -41,8 +41,8 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("wallace_pool.cuh", "wallace_pool_inst.hip", "wallace_kernels.hip",
-                 "wallace_internal.h"):
+    for name in ("wallace_pool.hpp", "wallace_devmath.hpp", "wallace_pool_inst.hip",
+                 "wallace_kernels.hip", "wallace_internal.h"):
         with open(os.path.join(ROOT, "paper_1004_3114_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

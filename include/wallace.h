@@ -100,7 +100,8 @@ void wallace_default_opts(wallace_opts *opts);
 const char *wallace_strerror(int32_t code);
 
 /* Text of the last HIP runtime error behind a WALLACE_EHIP return in the
- * calling thread (empty if none). Valid until the next call in the thread. */
+ * calling thread, or of the limit behind wallace_fill_static's
+ * WALLACE_ENOSPC (empty if none). Valid until the next call in the thread. */
 const char *wallace_last_error(void);
 
 /* ---- single generator ------------------------------------------------------ */
@@ -145,6 +146,24 @@ int32_t wallace_fill(wallace_gen *g, float *d_out, uint64_t count, void *stream)
  * multiply then one FP32 add) for N(mu, sigma^2) output (section 7). */
 int32_t wallace_fill_normal(wallace_gen *g, float *d_out, uint64_t count,
                             float mu, float sigma, void *stream);
+
+/* For callers that cannot allocate device memory or must not touch a
+ * workspace's scratch regions (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same as wallace_fill, with
+ * the call's scratch (a streamed pool's partial sums of squares, component
+ * nodes and last-value slots; the sum-of-squares tree of restarts and
+ * workspace checks) taken from a static device array of
+ * WALLACE_STATIC_SCRATCH_BYTES bytes (4 MiB) that the library holds on
+ * each GPU it runs on until the process ends, instead of from the
+ * workspace. The generator's state and pools stay in its workspace. Output,
+ * stream position and state are identical to wallace_fill's. Allocates
+ * nothing. A generator whose scratch exceeds the array returns
+ * WALLACE_ENOSPC (no supported shape needs more than about 2 MiB). Every
+ * call on a GPU shares that GPU's array: calls that overlap in time on one
+ * GPU (different streams, or different host threads) race and must be
+ * ordered by the caller. */
+#define WALLACE_STATIC_SCRATCH_BYTES (4u << 20)
+int32_t wallace_fill_static(wallace_gen *g, float *d_out, uint64_t count, void *stream);
 
 /* Reads the current pool's sum of squares (as used for the next pass's
  * scale) and the number of passes done. Synchronises `stream`. */

@@ -30,7 +30,8 @@ SOURCES = [("wallace_kernels.hip", [], "wallace_kernels"),
            ("wallace_stream.hip", [], "wallace_stream"),
            ("wallace_host.cpp", [], "wallace_host"),
            ("wallace_batch.cpp", [], "wallace_batch"),
-           ("wallace_tune.cpp", [], "wallace_tune")]
+           ("wallace_tune.cpp", [], "wallace_tune"),
+           ("wallace_static.hip", [], "wallace_static")]
 for _n in (2, 4, 16):
     for _rm in (0, 1, 2):
         SOURCES.append(("wallace_pool_inst.hip",

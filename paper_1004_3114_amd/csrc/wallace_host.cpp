@@ -64,6 +64,11 @@ int32_t hip_fail(hipError_t e, const char *where)
     return WALLACE_EHIP;
 }
 
+void record_error(const char *what)
+{
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s", what);
+}
+
 const char *last_error_text() { return g_last_error; }
 
 bool pow2(uint64_t x) { return x && !(x & (x - 1)); }

@@ -16,6 +16,8 @@ uint64_t host_splitmix_next(uint64_t &s);
 void host_box_muller(uint64_t seed, size_t nu, float *pool, uint64_t *rng_after);
 // Records the HIP error text for wallace_last_error and returns WALLACE_EHIP.
 int32_t hip_fail(hipError_t e, const char *where);
+// Records a non-HIP error text for wallace_last_error.
+void record_error(const char *what);
 bool pow2(uint64_t x);
 int ilog2(uint64_t x);
 bool shape_ok(int n, uint32_t N);

@@ -66,6 +66,7 @@ SIGNATURES = {
     "wallace_initial_pool": (_i32, [_u64, _i32, _u32, _vp, ctypes.POINTER(_u64)]),
     "wallace_fill": (_i32, [_vp, _vp, _u64, _vp]),
     "wallace_fill_normal": (_i32, [_vp, _vp, _u64, _f32, _f32, _vp]),
+    "wallace_fill_static": (_i32, [_vp, _vp, _u64, _vp]),
     "wallace_sumsq": (_i32, [_vp, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(_u64), _vp]),
     "wallace_read_pool": (_i32, [_vp, _vp, _vp]),
@@ -205,6 +206,15 @@ class Generator:
         assert out.dtype.itemsize == 4 and out.is_contiguous() and out.numel() >= count
         _check(lib().wallace_fill(self._h, out.data_ptr(), count, _stream_handle(stream)),
                "wallace_fill")
+        return out
+
+    def fill_static(self, out, count: Optional[int] = None, stream=None):
+        """As fill, with the call's scratch in the library's static device
+        array instead of the workspace (wallace_fill_static)."""
+        count = out.numel() if count is None else count
+        assert out.dtype.itemsize == 4 and out.is_contiguous() and out.numel() >= count
+        _check(lib().wallace_fill_static(self._h, out.data_ptr(), count,
+                                         _stream_handle(stream)), "wallace_fill_static")
         return out
 
     def fill_normal(self, out, mu: float, sigma: float, count: Optional[int] = None,

@@ -127,6 +127,7 @@ def test_init_argument_errors_before_gpu():
 def test_null_handles():
     L = W.lib()
     assert L.wallace_fill(None, 256, 10, None) == W.WALLACE_EINVAL
+    assert L.wallace_fill_static(None, 256, 10, None) == W.WALLACE_EINVAL
     assert L.wallace_sumsq(None, None, None, None) == W.WALLACE_EINVAL
     assert L.wallace_destroy(None) == W.WALLACE_OK
     assert L.wallace_batch_destroy(None) == W.WALLACE_OK

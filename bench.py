@@ -28,6 +28,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -133,7 +135,10 @@ def headline(torch, W, workloads, steps, warmup):
                                       "normals_per_step": total}
 
 
-def single_pool(torch, W, workloads, which, reps=3):
+def single_pool(torch, W, workloads, which, reps=3, keep=None):
+    """Times one fill of the whole workload on a fresh generator (best of
+    reps after one untimed run). keep: receives the last generator's final
+    pool, sum of squares and pass count."""
     spec = workloads.SINGLE_SMALL if which == "small" else workloads.SINGLE_LARGE
     log(f"single pool {spec.name}: n={spec.n} N={spec.N} passes={spec.passes}")
     out = torch.empty(spec.normals, dtype=torch.float32, device="cuda")
@@ -145,6 +150,9 @@ def single_pool(torch, W, workloads, which, reps=3):
         ms = timed_events(torch, stream, lambda: g.fill(out), 1)[0]
         if r > 0:
             best = ms if best is None else min(best, ms)
+        if r == reps and keep is not None:
+            keep["pool"] = g.pool()
+            keep["sigma"], keep["passes"] = g.sumsq()
         del g
     del out
     torch.cuda.empty_cache()
@@ -192,62 +200,147 @@ def uneven(torch, W, workloads, reps=3):
             "frac_hbm": round(rate * 4 / 1e9 / HBM_PEAK_GBPS, 4)}
 
 
-def store_ceiling(torch, nbytes=16 << 30, reps=5):
-    """Plain streaming-store reference on the same GPU (torch fill kernel)."""
+def store_ceilings(torch, nbytes=16 << 30, reps=5):
+    """Plain store streams on the same GPU, GB/s (best of reps over 16 GiB):
+    torch's fill kernel; the store-ceiling kernels of libwallace_check.so in
+    one-shot form (one 16-byte chunk per thread, blocks in address order,
+    nontemporal and plain); and long-lived waves writing the headline's own
+    pattern with no arithmetic (65,536 waves, each 64 consecutive 4 KB
+    pools)."""
+    from paper_1004_3114_amd import check as CK
     t = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
     t.fill_(1.0)
-    ms = min(timed_events(torch, stream, lambda: t.fill_(0.5), reps))
+
+    def rate(fn):
+        fn()
+        ms = min(timed_events(torch, stream, fn, reps))
+        return round(nbytes / (ms * 1e-3) / 1e9, 1)
+
+    waves, chunks = 65536, 64
+    assert waves * chunks * 1024 * 4 == nbytes
+    res = {"torch_fill": rate(lambda: t.fill_(0.5)),
+           "oneshot_nontemporal": rate(lambda: CK.store_oneshot(t, 0.25, True)),
+           "oneshot": rate(lambda: CK.store_oneshot(t, 0.25, False)),
+           "longlived_headline_pattern": rate(
+               lambda: CK.store_longlived(t, waves, chunks, chunks * 1024, 1024))}
     del t
     torch.cuda.empty_cache()
-    return round(nbytes / (ms * 1e-3) / 1e9, 1)
+    return res
 
 
-def cpu_baseline(workloads, budget_s=12.0):
-    """The oracle as it is, one generator per worker process, on a bounded
-    sample of the batched uniform workload (full 256 passes per generator)."""
+def precision_report(small, large):
+    """Precision of the single pools after their full pass counts, from the
+    GPU's final pools (small/large: the kept pool, sum of squares and pass
+    count) and the oracle results the CPU-baseline leg kept: bit-equality
+    with the FP32 oracle (SHA-256 of the pool), the drift of the pool's
+    exact sum of squares from the chi-squared target S of its last pass
+    (section 4), the library's sum of squares against that exact sum, and
+    for the small pool the per-variate error e = |x32 - x64| / max(1, |x64|)
+    against the FP64 oracle (bound 1e-5)."""
+    out = {}
+    for name, got in (("single_small", small), ("single_large", large)):
+        if not got or f"{name}_fp32_S" not in PRECISION_REF:
+            continue
+        pool = got["pool"]
+        d = pool.astype(np.float64)
+        exact = float(np.sum(d * d))
+        S = PRECISION_REF[f"{name}_fp32_S"]
+        rec = {"passes": int(got["passes"]),
+               "bit_exact_vs_fp32_oracle":
+                   hashlib.sha256(pool.tobytes()).hexdigest() == PRECISION_REF[f"{name}_fp32_sha"],
+               "sigma_drift": abs(exact - S) / S,
+               "sigma_lib_rel_err": abs(got["sigma"] - exact) / exact}
+        x64 = PRECISION_REF.get(f"{name}_fp64_pool")
+        if x64 is not None:
+            e = np.abs(d - x64) / np.maximum(1.0, np.abs(x64))
+            rec.update({"vs": "FP64 oracle", "err_max": float(e.max()),
+                        "err_rms": float(np.sqrt(np.mean(e * e))), "bound": 1e-5,
+                        "within_bound": bool(e.max() <= 1e-5)})
+        out[name] = rec
+    return out
+
+
+# Host cores one GPU's job may use on the measuring machines (each GPU box
+# gives one GPU's job a 16-core share, whatever the host reports in total).
+CPU_SHARE = 16
+
+
+def host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count() or 1, "affinity": affinity}
+
+
+def cpu_baseline(workloads):
+    """The oracle as it is, on the host cores: the headline workload
+    (batch_uniform) and the uneven batch in full, one generator per worker
+    process on the job's core share; the two single pools in full on one
+    thread; the FP64 oracle of the single small pool, whose last pool is kept
+    for the precision report."""
     import multiprocessing as mp
 
     import oracle  # the CPU-baseline leg may use the oracle
     oracle.lib()
-    cores = max(1, min(16, os.cpu_count() or 1))
-    spec = workloads.batch_uniform()
-    passes = 64 * spec.launches
-    per_gen = 1024 * passes
-    chunk = cores * 4
-    done = 0
-    t0 = time.perf_counter()
+    info = host_info()
+    cores = max(1, min(CPU_SHARE, info["affinity"]))
+    res = {}
     with mp.get_context("spawn").Pool(cores) as pool:
-        g0 = 0
-        while time.perf_counter() - t0 < budget_s and g0 < spec.G:
-            seeds = [int(s) for s in spec.seeds[g0:g0 + chunk]]
-            pool.map(_cpu_one, [(s, passes) for s in seeds])
-            done += len(seeds)
-            g0 += chunk
-    wall = time.perf_counter() - t0
-    return {"value": done * per_gen / wall, "unit": "normals/s", "cores": cores,
+        pool.map(_cpu_warm, range(cores))
+        for spec in (workloads.batch_uniform(), workloads.batch_uneven()):
+            passes = spec.passes.astype(np.uint64) * spec.launches
+            work = spec.nu * passes
+            order = np.argsort(-work.astype(np.float64), kind="stable")  # largest first
+            args = [(int(spec.seeds[g]), int(spec.n[g]), int(spec.N[g]), int(passes[g]))
+                    for g in order]
+            t0 = time.perf_counter()
+            pool.map(_cpu_one, args, chunksize=max(1, len(args) // (cores * 64)))
+            wall = time.perf_counter() - t0
+            total = int(work.sum())
+            res[spec.name] = {"normals_per_s": total / wall, "normals": total,
+                              "wall_s": round(wall, 2),
+                              "sample": f"all {spec.G} generators in full, largest first, "
+                                        f"one generator per task on {cores} processes"}
+    res.update(cpu_single_thread(workloads))
+    head = res["batch_uniform"]
+    return {"value": head["normals_per_s"], "unit": "normals/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{done} of {spec.G} batch_uniform generators (n=4, N=256, seeds 42+g), "
-                      f"{passes} passes each = {done * per_gen} normals, one generator per "
-                      f"process on {cores} processes, {wall:.1f} s wall",
-            "single_thread": cpu_single_thread(workloads)}
+            "sample": f"batch_uniform in full ({head['normals']} normals), {head['sample']}, "
+                      f"{head['wall_s']} s wall",
+            "host": {**info, "core_share": CPU_SHARE},
+            "workloads": res}
 
 
 def cpu_single_thread(workloads):
-    """The oracle on one thread of this process: the single small pool in
-    full, the single large pool on a sample of its passes (its initial pool
-    not timed), and batch_uniform generators one after another."""
+    """The oracle on one thread of this process: both single pools in full
+    (the initial pool not timed), batch_uniform generators one after another,
+    and the FP64 oracle of the single small pool (its last pool is kept)."""
     import oracle
     oracle.lib()
     res = {}
-    for spec, sample_passes in ((workloads.SINGLE_SMALL, None), (workloads.SINGLE_LARGE, 5)):
-        P = spec.passes if sample_passes is None else sample_passes
+    for spec in (workloads.SINGLE_SMALL, workloads.SINGLE_LARGE):
         g = oracle.Gen(spec.seed, spec.n, spec.N)
         t0 = time.perf_counter()
-        g.fill(spec.n * spec.N * P)
+        for _ in range(spec.passes):
+            g.fill(spec.nu)  # one pass and its returned pool
         dt = time.perf_counter() - t0
-        res[spec.name] = {"normals_per_s": spec.n * spec.N * P / dt,
-                          "sample": f"{P} of {spec.passes} passes"}
+        res[spec.name] = {"normals_per_s": spec.normals / dt, "normals": spec.normals,
+                          "wall_s": round(dt, 2),
+                          "sample": f"all {spec.passes} passes on 1 thread"}
+        PRECISION_REF[f"{spec.name}_fp32_S"] = g.last_S
+        PRECISION_REF[f"{spec.name}_fp32_sha"] = hashlib.sha256(g.pool.tobytes()).hexdigest()
+        del g
     uni = workloads.batch_uniform()
     passes = 64 * uni.launches
     gens = 64
@@ -255,17 +348,37 @@ def cpu_single_thread(workloads):
     for s in uni.seeds[:gens]:
         oracle.Gen(int(s), 4, 256).fill(1024 * passes)
     dt = time.perf_counter() - t0
-    res["batch_uniform"] = {"normals_per_s": gens * 1024 * passes / dt,
-                            "sample": f"{gens} of {uni.G} generators, {passes} passes each, "
-                                      "initial pools included"}
+    res["batch_uniform_1thread"] = {"normals_per_s": gens * 1024 * passes / dt,
+                                    "sample": f"{gens} of {uni.G} generators, {passes} passes "
+                                              "each, initial pools included, 1 thread"}
+    spec = workloads.SINGLE_SMALL
+    g64 = oracle.Gen64(spec.seed, spec.n, spec.N)
+    t0 = time.perf_counter()
+    for _ in range(spec.passes):
+        g64.fill(spec.nu)
+    dt = time.perf_counter() - t0
+    res["single_small_fp64"] = {"normals_per_s": spec.normals / dt,
+                                "sample": f"FP64 variant, all {spec.passes} passes, 1 thread"}
+    PRECISION_REF["single_small_fp64_pool"] = g64.pool
     return res
+
+
+# FP64 oracle results kept by the CPU-baseline leg for the precision report
+PRECISION_REF = {}
+
+
+def _cpu_warm(_):
+    import oracle
+    oracle.lib()
+    return 0
 
 
 def _cpu_one(arg):
     import oracle
-    seed, passes = arg
-    g = oracle.Gen(seed, 4, 256)
-    g.fill(1024 * passes)
+    seed, n, N, passes = arg
+    g = oracle.Gen(seed, n, N)
+    for _ in range(passes):
+        g.fill(n * N)  # one pass and its returned pool
     return 0
 
 
@@ -328,11 +441,15 @@ def main():
             "config": {"workload": "batch_uniform", **cfg},
             "roofline": roof}
     if args.only == "all":
-        line["single_pool"] = {"single_small": single_pool(torch, W, workloads, "small"),
-                               "single_large": single_pool(torch, W, workloads, "large")}
+        small, large = {}, {}
+        line["single_pool"] = {
+            "single_small": single_pool(torch, W, workloads, "small", keep=small),
+            "single_large": single_pool(torch, W, workloads, "large", keep=large)}
         line["batch_uneven"] = uneven(torch, W, workloads)
-        line["store_ceiling_GBps"] = store_ceiling(torch)
-        line["frac_of_store_ceiling"] = round(roof["achieved"] / line["store_ceiling_GBps"], 4)
+        line["precision"] = precision_report(small, large)
+        ceil = store_ceilings(torch)
+        line["store_ceilings_GBps"] = ceil
+        line["frac_of_store_ceiling"] = {k: round(roof["achieved"] / v, 4) for k, v in ceil.items()}
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 

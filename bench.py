@@ -16,6 +16,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --only single_small (profiling runs: one small pool only)
        python bench.py --only single_large (profiling runs: streamed pool only)
        python bench.py --only uneven       (profiling runs: uneven batch only)
+       python bench.py --only headline_candidates (every compiled schedule of the
+                                           headline class, then the autotuner's pick)
        python bench.py --copy-probe BYTES  (calibration copy for counters)
 """
 from __future__ import annotations
@@ -133,6 +135,58 @@ def headline(torch, W, workloads, steps, warmup):
     return value, ms_per_step, roof, {"G": spec.G, "n": 4, "N": 256, "passes_per_launch": 64,
                                       "launches_per_step": spec.launches,
                                       "normals_per_step": total}
+
+
+def headline_candidates(torch, W, workloads, reps=5):
+    """The headline workload under every compiled pool-resident schedule of
+    its class (n = 4, N = 256): T tuples per lane on L = 256 / T lanes, C
+    components per on-chip stage, forced through WALLACE_SCHED; ms per
+    launch (median of reps graph replays of 4 launches). Then the library's
+    autotuner on the same batch, and the schedule it picks."""
+    spec = workloads.batch_uniform()
+    per = spec.normals_per_launch()
+    alg = per * (BYTES_PER_NORMAL + 2 * 4 * 1024 / (64 * 1024))
+    out = torch.empty(per * spec.launches, dtype=torch.float32, device="cuda")
+    rows = []
+    saved = os.environ.get("WALLACE_SCHED")
+    try:
+        for T in (1, 2, 4, 8, 16):
+            for C in (4, 2):
+                os.environ["WALLACE_SCHED"] = f"4:256:{T}:{256 // T}:{C}"
+                try:
+                    b = W.Batch(spec.seeds, spec.n, spec.N)
+                except W.WallaceError:
+                    continue  # not a compiled shape
+                b.plan(spec.offsets(), spec.passes)
+                graph = torch.cuda.CUDAGraph()
+                stream = torch.cuda.Stream()
+                with torch.cuda.graph(graph, stream=stream):
+                    cur = torch.cuda.current_stream()
+                    for launch in range(spec.launches):
+                        b.fill(out[launch * per:], stream=cur)
+                graph.replay()
+                torch.cuda.synchronize()
+                rs = torch.cuda.current_stream()
+                ms = sorted(timed_events(torch, rs, graph.replay, reps))
+                launch_ms = ms[len(ms) // 2] / spec.launches
+                rows.append({"T": T, "L": 256 // T, "C": C, "ms_per_launch": round(launch_ms, 4),
+                             "GBps": round(alg / (launch_ms * 1e-3) / 1e9, 1)})
+                log(f"candidate T={T} L={256 // T} C={C}: {launch_ms:.4f} ms per launch")
+                del graph, b
+    finally:
+        if saved is None:
+            os.environ.pop("WALLACE_SCHED", None)
+        else:
+            os.environ["WALLACE_SCHED"] = saved
+    b = W.Batch(spec.seeds, spec.n, spec.N)
+    default = b.classes()[0]
+    b.tune()
+    tuned = b.classes()[0]
+    del b, out
+    torch.cuda.empty_cache()
+    return {"workload": "batch_uniform", "candidates": rows,
+            "default": {k: default[k] for k in ("T", "L", "C")},
+            "tuner_pick": {k: tuned[k] for k in ("T", "L", "C")}}
 
 
 def single_pool(torch, W, workloads, which, reps=3, keep=None):
@@ -397,7 +451,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["headline", "single_small", "single_large", "uneven", "all"],
+    ap.add_argument("--only", choices=["headline", "single_small", "single_large", "uneven",
+                                       "headline_candidates", "all"],
                     default="all")
     ap.add_argument("--copy-probe", type=int, default=0)
     args = ap.parse_args()
@@ -431,6 +486,9 @@ def main():
         return
     if args.only == "uneven":
         print(json.dumps(uneven(torch, W, workloads)), flush=True)
+        return
+    if args.only == "headline_candidates":
+        print(json.dumps(headline_candidates(torch, W, workloads)), flush=True)
         return
     value, ms_per_step, roof, cfg = headline(torch, W, workloads, args.steps, args.warmup)
     line = {"metric": "normals/sec at 1 GPU (FP32) + % HBM-write roofline; batched vs single-pool",

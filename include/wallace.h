@@ -211,15 +211,28 @@ int32_t wallace_batch_plan(wallace_batch *b, const uint64_t *offsets,
 
 /* Runs the planned passes for all generators. Each (n, N) class of the
  * batch is one launch of its pool-resident kernel, whose blocks take the
- * class's jobs largest first; the classes are spread over `stream` and up
+ * class's jobs largest first. The classes are spread over `stream` and up
  * to three side streams forked from it and joined back into it (parallel
- * branches under graph capture). Allocates nothing, copies nothing from the
- * host and never synchronises, so it can be captured into a HIP graph; every
- * call advances every generator. d_out must be 16-byte aligned and hold
- * out_len floats; out_len below the planned extent (the largest
- * offsets[g] + passes[g]*n[g]*N[g]) returns WALLACE_EINVAL before anything
- * is enqueued. */
+ * branches under graph capture): classes of pools with at most 8192 values,
+ * whose time is set by their longest chain of passes, run first on
+ * `stream`; the others go largest first onto the least loaded side stream.
+ * The side streams are the caller's (wallace_batch_set_streams) or else
+ * created by the library at the first fill that needs them. Allocates no
+ * memory, copies nothing from the host and never synchronises, so it can be
+ * captured into a HIP graph; every call advances every generator. d_out must
+ * be 16-byte aligned and hold out_len floats; out_len below the planned
+ * extent (the largest offsets[g] + passes[g]*n[g]*N[g]) returns
+ * WALLACE_EINVAL before anything is enqueued. */
 int32_t wallace_fill_batched(wallace_batch *b, float *d_out, uint64_t out_len, void *stream);
+
+/* Side streams for wallace_fill_batched (section 9: independent generators
+ * can run side by side): count (<= 3) hipStream_t handles owned by the
+ * caller, which must keep them alive while fills that use them are pending
+ * and must not pass a fill's own `stream` among them. count = 0 returns to
+ * streams the library creates itself (the default). With fewer side streams
+ * than classes need, fills use the ones given. Host call; enqueues
+ * nothing. */
+int32_t wallace_batch_set_streams(wallace_batch *b, uint32_t count, void *const *streams);
 
 /* Autotuner: for every (n, N) class in the batch, times each candidate
  * schedule (lanes per pool, components per on-chip stage) on copies of the

@@ -83,6 +83,7 @@ SIGNATURES = {
                                    ctypes.POINTER(_u64), _vp]),
     "wallace_batch_classes": (_i32, [_vp, _u32, _vp, ctypes.POINTER(_u32)]),
     "wallace_batch_status": (_i32, [_vp, ctypes.POINTER(_u32), _vp]),
+    "wallace_batch_set_streams": (_i32, [_vp, _u32, ctypes.POINTER(_vp)]),
     "wallace_batch_destroy": (_i32, [_vp]),
 }
 
@@ -269,6 +270,17 @@ class Batch:
                                         b.value, _stream_handle(stream), ctypes.byref(h)),
                "wallace_batch_init")
         self._h = h
+        # side streams for fills of several (n, N) classes, owned by torch
+        self.side_streams = [torch.cuda.Stream(device=dev) for _ in range(3)]
+        self.set_streams(self.side_streams)
+
+    def set_streams(self, streams):
+        """Hand the batch up to three side streams (torch streams) for its
+        fills; an empty list returns to streams the library creates."""
+        arr = (_vp * max(len(streams), 1))(*[int(x.cuda_stream) for x in streams])
+        _check(lib().wallace_batch_set_streams(self._h, len(streams), arr),
+               "wallace_batch_set_streams")
+        self._streams_held = list(streams)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -62,6 +62,45 @@ def test_mixed_small_batch_two_launches():
     assert b.status() == (0, 0)
 
 
+def test_mixed_batch_side_stream_choices():
+    # the classes of a fill run on the caller's side streams (torch's, the
+    # binding's default), on streams the library creates, or on fewer side
+    # streams than classes: latency-bound classes (pools of <= 8192 values)
+    # first on the fill's stream, the others beside them; every choice must
+    # continue each generator's stream exactly
+    _dev()
+    shapes = [(4, 64), (16, 64), (4, 512), (4, 4096), (16, 1024), (4, 16384), (16, 4096)]
+    G = 21
+    n = np.array([shapes[g % len(shapes)][0] for g in range(G)], dtype=np.int32)
+    N = np.array([shapes[g % len(shapes)][1] for g in range(G)], dtype=np.uint32)
+    seeds = np.arange(900, 900 + G, dtype=np.uint64)
+    passes = (np.arange(G) % 3 + 1).astype(np.uint32)
+    sizes = n.astype(np.uint64) * N * passes
+    off = np.zeros(G, np.uint64)
+    np.cumsum(sizes[:-1], out=off[1:])
+    total = int(sizes.sum())
+    print(f"case side streams G={G} total={total}", flush=True)
+    b = W.Batch(seeds, n, N)
+    b.plan(off, passes)
+    refs = [oracle.Gen(int(seeds[g]), int(n[g]), int(N[g])) for g in range(G)]
+    one = torch.cuda.Stream()
+    for choice in ("torch", "library", "one", "torch"):
+        if choice == "library":
+            b.set_streams([])
+        elif choice == "one":
+            b.set_streams([one])
+        else:
+            b.set_streams(b.side_streams)
+        out = torch.full((total,), float("nan"), dtype=torch.float32, device="cuda")
+        b.fill(out)
+        torch.cuda.synchronize()
+        host = out.cpu().numpy()
+        for g in range(G):
+            assert_bits_equal(host[int(off[g]):int(off[g]) + int(sizes[g])],
+                              refs[g].fill(int(sizes[g])), f"{choice} gen {g} n={n[g]} N={N[g]}")
+    assert b.status() == (0, 0)
+
+
 def test_mixed_batch_graph_replays():
     # classes run on forked streams; captured in a graph, the fork and join
     # become parallel branches. Every replay continues each generator's

@@ -18,6 +18,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --only uneven       (profiling runs: uneven batch only)
        python bench.py --only headline_candidates (every compiled schedule of the
                                            headline class, then the autotuner's pick)
+       python bench.py --only precision_shape (n = 16, N = 2^20 pass: butterflies
+                                           against the matrix-core transform)
        python bench.py --copy-probe BYTES  (calibration copy for counters)
 """
 from __future__ import annotations
@@ -187,6 +189,30 @@ def headline_candidates(torch, W, workloads, reps=5):
     return {"workload": "batch_uniform", "candidates": rows,
             "default": {k: default[k] for k in ("T", "L", "C")},
             "tuner_pick": {k: tuned[k] for k in ("T", "L", "C")}}
+
+
+def precision_shape(torch, W, workloads, passes=50, reps=3):
+    """The long-run precision workload's pass (n = 16, N = 2^20, seed 42) with
+    the butterflies and with the matrix-core transform: microseconds per pass
+    over a fill of `passes` returned pools (best of reps, fresh generator
+    each time)."""
+    spec = workloads.PRECISION
+    out = torch.empty(passes * spec.nu, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {"workload": spec.name, "n": spec.n, "N": spec.N, "passes_timed": passes}
+    for tm, name in ((0, "butterflies"), (1, "matrix_cores")):
+        best = None
+        for r in range(reps + 1):
+            g = W.Generator(spec.seed, spec.n, spec.N, transform_mode=tm)
+            torch.cuda.synchronize()
+            ms = timed_events(torch, stream, lambda: g.fill(out), 1)[0]
+            if r > 0:
+                best = ms if best is None else min(best, ms)
+            del g
+        res[f"{name}_us_per_pass"] = round(best * 1e3 / passes, 2)
+    del out
+    torch.cuda.empty_cache()
+    return res
 
 
 def single_pool(torch, W, workloads, which, reps=3, keep=None):
@@ -452,7 +478,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--only", choices=["headline", "single_small", "single_large", "uneven",
-                                       "headline_candidates", "all"],
+                                       "headline_candidates", "precision_shape", "all"],
                     default="all")
     ap.add_argument("--copy-probe", type=int, default=0)
     args = ap.parse_args()
@@ -487,6 +513,9 @@ def main():
     if args.only == "uneven":
         print(json.dumps(uneven(torch, W, workloads)), flush=True)
         return
+    if args.only == "precision_shape":
+        print(json.dumps(precision_shape(torch, W, workloads)), flush=True)
+        return
     if args.only == "headline_candidates":
         print(json.dumps(headline_candidates(torch, W, workloads)), flush=True)
         return
@@ -505,6 +534,7 @@ def main():
             "single_large": single_pool(torch, W, workloads, "large", keep=large)}
         line["batch_uneven"] = uneven(torch, W, workloads)
         line["precision"] = precision_report(small, large)
+        line["precision"]["n16_transform"] = precision_shape(torch, W, workloads)
         ceil = store_ceilings(torch)
         line["store_ceilings_GBps"] = ceil
         line["frac_of_store_ceiling"] = {k: round(roof["achieved"] / v, 4) for k, v in ceil.items()}

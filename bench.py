@@ -272,12 +272,24 @@ def uneven(torch, W, workloads, reps=3):
     stream = torch.cuda.current_stream()
     b.fill(out)
     ms = min(timed_events(torch, stream, lambda: b.fill(out), reps))
-    del out, b
+    # the same fill captured in a HIP graph (its side streams become parallel
+    # branches), replayed
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    with torch.cuda.graph(graph, stream=cap):
+        b.fill(out, stream=torch.cuda.current_stream())
+    graph.replay()
+    torch.cuda.synchronize()
+    gms = min(timed_events(torch, torch.cuda.current_stream(), graph.replay, reps))
+    classes = b.classes()
+    del graph, out, b
     torch.cuda.empty_cache()
     rate = total / (ms * 1e-3)
     return {"workload": "batch_uneven", "G": spec.G, "normals": total, "ms": round(ms, 3),
             "normals_per_s": rate, "write_GBps": round(rate * 4 / 1e9, 1),
-            "frac_hbm": round(rate * 4 / 1e9 / HBM_PEAK_GBPS, 4)}
+            "frac_hbm": round(rate * 4 / 1e9 / HBM_PEAK_GBPS, 4),
+            "graph_ms": round(gms, 3), "graph_normals_per_s": total / (gms * 1e-3),
+            "classes": classes}
 
 
 def store_ceilings(torch, nbytes=16 << 30, reps=5):

@@ -24,6 +24,9 @@ CASES = [
     (16, 1 << 13, {"check_workspace": 1}, 2 * 16 * (1 << 13) + 5, 16 * (1 << 13) - 3),
     (2, 1 << 16, {"restart_passes": 2}, 5 * 2 * (1 << 16), 2 * (1 << 16) + 9),
     (4, 1024, {"restart_passes": 4}, 9 * 4096 + 100, 3 * 4096),
+    # the largest scratch of any supported shape: n = 16, N = 2^22 streamed
+    # (4096 partial nodes per component) with the 2^26-value check tree
+    (16, 1 << 22, {"check_workspace": 1}, 16 * (1 << 22) + 5, 16 * (1 << 22) - 2),
 ]
 
 

@@ -353,8 +353,9 @@ def precision_report(small, large):
     return out
 
 
-# Host cores one GPU's job may use on the measuring machines (each GPU machine
-# gives one GPU's job a 16-core share, whatever the host reports in total).
+# Host cores the CPU baseline uses at most: one GPU's share of the host on
+# the MI355X machines measured (16 cores per GPU, whatever the host reports
+# in total).
 CPU_SHARE = 16
 
 

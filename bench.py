@@ -90,8 +90,13 @@ def headline(torch, W, workloads, steps, warmup):
     t0 = time.time()
     b = W.Batch(spec.seeds, spec.n, spec.N)
     b.plan(spec.offsets(), spec.passes)
-    log(f"init {time.time() - t0:.1f}s; output {total * 4 / 2**30:.0f} GiB")
     out = torch.empty(total, dtype=torch.float32, device="cuda")
+    # the class's schedule, picked by the library's autotuner on the planned
+    # launch itself (the generators' state is left as it is)
+    b.tune_planned(out[:per])
+    sched = {k: b.classes()[0][k] for k in ("T", "L", "C")}
+    log(f"init and tuning {time.time() - t0:.1f}s (schedule {sched}); "
+        f"output {total * 4 / 2**30:.0f} GiB")
     stream = torch.cuda.Stream()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=stream):
@@ -129,14 +134,15 @@ def headline(torch, W, workloads, steps, warmup):
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": counter_traffic(khash),
-            "kernel": "k_pool<4,4> (n=4, T=4 tuples/lane, L=64 lanes/pool)",
+            "kernel": f"k_pool<4,{sched['T']},{sched['L']}> (n=4, T tuples/lane, L lanes/pool)",
             "alg_bytes_per_launch": int(alg_bytes), "avg_launch_ms": round(launch_ms, 4),
             "kernel_source_hash": khash}
     del graph, out
     torch.cuda.empty_cache()
     return value, ms_per_step, roof, {"G": spec.G, "n": 4, "N": 256, "passes_per_launch": 64,
                                       "launches_per_step": spec.launches,
-                                      "normals_per_step": total}
+                                      "normals_per_step": total,
+                                      "schedule": {**sched, "picked_by": "autotuner"}}
 
 
 def headline_candidates(torch, W, workloads, reps=5):
@@ -144,7 +150,7 @@ def headline_candidates(torch, W, workloads, reps=5):
     its class (n = 4, N = 256): T tuples per lane on L = 256 / T lanes, C
     components per on-chip stage, forced through WALLACE_SCHED; ms per
     launch (median of reps graph replays of 4 launches). Then the library's
-    autotuner on the same batch, and the schedule it picks."""
+    autotuner on the planned launch, and the schedule it picks."""
     spec = workloads.batch_uniform()
     per = spec.normals_per_launch()
     alg = per * (BYTES_PER_NORMAL + 2 * 4 * 1024 / (64 * 1024))
@@ -182,7 +188,8 @@ def headline_candidates(torch, W, workloads, reps=5):
             os.environ["WALLACE_SCHED"] = saved
     b = W.Batch(spec.seeds, spec.n, spec.N)
     default = b.classes()[0]
-    b.tune()
+    b.plan(spec.offsets(), spec.passes)
+    b.tune_planned(out[:per])
     tuned = b.classes()[0]
     del b, out
     torch.cuda.empty_cache()
@@ -264,11 +271,11 @@ def uneven(torch, W, workloads, reps=3):
     total = spec.normals_per_launch()
     log(f"batch_uneven: G={spec.G} normals={total}")
     b = W.Batch(spec.seeds, spec.n, spec.N)
-    t0 = time.time()
-    b.tune()  # per (n, N) class: the fastest pool-resident schedule
-    log(f"batch_uneven tuned in {time.time() - t0:.1f}s")
     b.plan(spec.offsets(), spec.passes)
     out = torch.empty(total, dtype=torch.float32, device="cuda")
+    t0 = time.time()
+    b.tune_planned(out)  # per (n, N) class: the fastest schedule on its planned jobs
+    log(f"batch_uneven tuned in {time.time() - t0:.1f}s")
     stream = torch.cuda.current_stream()
     b.fill(out)
     ms = min(timed_events(torch, stream, lambda: b.fill(out), reps))
@@ -507,7 +514,7 @@ def main():
     # process loads the HIP runtime or touches the GPU
     cpu = None
     if args.only == "all" and not args.copy_probe:
-        log("cpu baseline (oracle, bounded sample)")
+        log("cpu baseline (the oracle on the host cores)")
         cpu = cpu_baseline(workloads)
 
     import torch

@@ -252,6 +252,18 @@ int32_t wallace_batch_tune_bytes(wallace_batch *b, size_t *bytes);
 int32_t wallace_batch_tune(wallace_batch *b, void *d_scratch,
                            size_t scratch_bytes, void *stream);
 
+/* Autotuner on the planned fill itself (after wallace_batch_plan): for every
+ * (n, N) class, runs the class's planned jobs (their pass counts and output
+ * offsets) under each candidate schedule, on a copy of every generator's
+ * state and pool in d_scratch (>= wallace_batch_tune_bytes), writing into
+ * d_out (>= the planned extent, 16-byte aligned; its contents are
+ * overwritten), and keeps the fastest for the class, as wallace_batch_tune
+ * does. Each class is timed alone. The generators' state is not touched, and
+ * every candidate gives the same bits. Synchronises. WALLACE_ESTATE before a
+ * plan. */
+int32_t wallace_batch_tune_planned(wallace_batch *b, float *d_out, uint64_t out_len,
+                                   void *d_scratch, size_t scratch_bytes, void *stream);
+
 /* Per-generator sum of squares and passes done; synchronises. */
 int32_t wallace_batch_sumsq(wallace_batch *b, uint32_t g, double *sigma,
                             uint64_t *passes, void *stream);

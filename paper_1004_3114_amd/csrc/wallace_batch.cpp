@@ -475,9 +475,70 @@ int32_t wallace_batch_destroy(wallace_batch *b)
 int32_t wallace_batch_tune_bytes(wallace_batch *b, size_t *bytes)
 {
     if (!b || !bytes) return WALLACE_EINVAL;
-    size_t m = 0;
+    size_t m = b->lay.jobs - b->lay.states;  // a copy of every state and pool
     for (const ClassInfo &c : b->classes) m = std::max(m, tune_scratch_bytes(c.n, c.N));
     *bytes = m;
+    return WALLACE_OK;
+}
+
+int32_t wallace_batch_tune_planned(wallace_batch *b, float *d_out, uint64_t out_len,
+                                   void *d_scratch, size_t scratch_bytes, void *stream)
+{
+    if (!b || !d_out || (((uintptr_t)d_out) & 15) || !d_scratch ||
+        (((uintptr_t)d_scratch) & (kAlign - 1)))
+        return WALLACE_EINVAL;
+    if (!b->planned) return WALLACE_ESTATE;
+    if (out_len < b->extent) return WALLACE_EINVAL;
+    // the states and pools regions are contiguous in the workspace; the
+    // candidates run on a copy of both, laid out the same way, so the plan's
+    // job table (state index, pool offset, output offset) serves unchanged
+    const size_t region = b->lay.jobs - b->lay.states;
+    if (scratch_bytes < region) return WALLACE_ENOSPC;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *copy = static_cast<char *>(d_scratch);
+    const uint32_t rm = (uint32_t)b->opts.reduce_mode;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipError_t e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    for (ClassInfo &c : b->classes) {
+        if (e != hipSuccess || c.job_count == 0) continue;
+        Sched cand[32];
+        const int nc = candidate_scheds(c.n, c.N, cand, 32);
+        float best_ms = 1e30f;
+        int best_i = -1;
+        for (int i = 0; i < nc && e == hipSuccess; ++i) {
+            ClassInfo t = c;
+            t.sched = cand[i];
+            e = class_grid(t, b->cus, rm);
+            if (e != hipSuccess) break;
+            PoolArgs a = class_args(b, t, d_out, 0);
+            a.states = reinterpret_cast<GenState *>(copy);
+            a.pools = reinterpret_cast<float *>(copy + (b->lay.pools - b->lay.states));
+            float ms = 0.0f;
+            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                e = hipMemcpyAsync(copy, b->ws + b->lay.states, region,
+                                   hipMemcpyDeviceToDevice, s);
+                if (e == hipSuccess) e = hipEventRecord(ev0, s);
+                if (e == hipSuccess) e = launch_pool(t.sched, a, t.grid, s);
+                if (e == hipSuccess) e = hipEventRecord(ev1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(ev1);
+                float ts = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ts, ev0, ev1);
+                if (rep > 0) ms = (rep == 1) ? ts : std::min(ms, ts);
+            }
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best_i = i;
+            }
+        }
+        if (e != hipSuccess || best_i < 0) break;
+        c.sched = cand[best_i];
+        e = class_grid(c, b->cus, rm);
+        record_tuned(c.n, c.N, c.sched, best_ms * 1000.0);
+    }
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (e != hipSuccess) return hip_fail(e, "wallace_batch_tune_planned");
     return WALLACE_OK;
 }
 

@@ -126,6 +126,13 @@ int forced_sched(int n, uint32_t N, Sched *out)
     return 0;
 }
 
+void record_tuned(int n, uint32_t N, const Sched &s, double us)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_cache_locked();
+    store_locked(n, N, s, us);
+}
+
 int tuned_sched(int n, uint32_t N, Sched *out)
 {
     if (const int f = forced_sched(n, N, out)) return f;

@@ -28,6 +28,10 @@ size_t tune_scratch_bytes(int n, uint32_t N);
 // Every supported schedule of the class.
 int candidate_scheds(int n, uint32_t N, Sched *out, int max);
 
+// Records a tuned schedule for (n, N) on this device (process cache and the
+// WALLACE_TUNE_CACHE file, if set).
+void record_tuned(int n, uint32_t N, const Sched &s, double us);
+
 // Times each candidate on copies of one generator (state + pool) placed in
 // scratch and stores the fastest in *best (and in the cache).
 int32_t tune_class(int n, uint32_t N, const wallace_opts &opts, const GenState *d_state,

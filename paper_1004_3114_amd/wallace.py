@@ -79,6 +79,7 @@ SIGNATURES = {
     "wallace_fill_batched": (_i32, [_vp, _vp, _u64, _vp]),
     "wallace_batch_tune_bytes": (_i32, [_vp, ctypes.POINTER(_sz)]),
     "wallace_batch_tune": (_i32, [_vp, _vp, _sz, _vp]),
+    "wallace_batch_tune_planned": (_i32, [_vp, _vp, _u64, _vp, _sz, _vp]),
     "wallace_batch_sumsq": (_i32, [_vp, _u32, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(_u64), _vp]),
     "wallace_batch_classes": (_i32, [_vp, _u32, _vp, ctypes.POINTER(_u32)]),
@@ -313,6 +314,20 @@ class Batch:
         ptr = (scratch.data_ptr() + 255) // 256 * 256
         _check(lib().wallace_batch_tune(self._h, ptr, b.value, _stream_handle(stream)),
                "wallace_batch_tune")
+
+    def tune_planned(self, out, stream=None):
+        """Autotune every class on the planned fill itself, writing into
+        `out` (checked like Batch.fill; its contents are overwritten)."""
+        import torch
+        check_batch_output(out, getattr(self, "extent", None), self.workspace.device)
+        b = _sz()
+        _check(lib().wallace_batch_tune_bytes(self._h, ctypes.byref(b)),
+               "wallace_batch_tune_bytes")
+        scratch = torch.empty(b.value + 256, dtype=torch.uint8, device=self.workspace.device)
+        ptr = (scratch.data_ptr() + 255) // 256 * 256
+        _check(lib().wallace_batch_tune_planned(self._h, out.data_ptr(), out.numel(), ptr,
+                                                b.value, _stream_handle(stream)),
+               "wallace_batch_tune_planned")
 
     def classes(self):
         """Per (n, N) class: its schedule (T, L, C), generator count and the

@@ -134,6 +134,7 @@ def test_null_handles():
     assert L.wallace_fill_batched(None, 256, 1 << 20, None) == W.WALLACE_EINVAL
     assert L.wallace_batch_plan(None, None, None, None) == W.WALLACE_EINVAL
     assert L.wallace_batch_set_streams(None, 0, None) == W.WALLACE_EINVAL
+    assert L.wallace_batch_tune_planned(None, 256, 1 << 20, 256, 1 << 20, None) == W.WALLACE_EINVAL
 
 
 def test_batch_output_checks_before_any_launch():

@@ -101,6 +101,43 @@ def test_mixed_batch_side_stream_choices():
     assert b.status() == (0, 0)
 
 
+def test_tuning_on_the_planned_fill_keeps_state_and_bits():
+    # wallace_batch_tune_planned runs every class's planned jobs under each
+    # candidate schedule on a copy of the states and pools, writing into the
+    # output: afterwards the generators are where they were, and the tuned
+    # fill continues every stream exactly
+    _dev()
+    shapes = [(4, 256), (4, 4096), (16, 64), (16, 2048), (2, 1024)]
+    G = 15
+    n = np.array([shapes[g % len(shapes)][0] for g in range(G)], dtype=np.int32)
+    N = np.array([shapes[g % len(shapes)][1] for g in range(G)], dtype=np.uint32)
+    seeds = np.arange(1300, 1300 + G, dtype=np.uint64)
+    passes = (np.arange(G) % 4 + 2).astype(np.uint32)
+    sizes = n.astype(np.uint64) * N * passes
+    off = np.zeros(G, np.uint64)
+    np.cumsum(sizes[:-1], out=off[1:])
+    total = int(sizes.sum())
+    print(f"case tune on the planned fill G={G} total={total}", flush=True)
+    b = W.Batch(seeds, n, N)
+    b.plan(off, passes)
+    before = [b.sumsq(g) for g in range(G)]
+    out = torch.zeros(total, dtype=torch.float32, device="cuda")
+    b.tune_planned(out)
+    assert [b.sumsq(g) for g in range(G)] == before
+    assert all(p == 0 for _, p in before)
+    out.fill_(float("nan"))
+    b.fill(out)
+    torch.cuda.synchronize()
+    host = out.cpu().numpy()
+    for g in range(G):
+        ref = oracle_generator_output(seeds[g], n[g], N[g], int(passes[g]))
+        assert_bits_equal(host[int(off[g]):int(off[g]) + int(sizes[g])], ref,
+                          f"gen {g} n={n[g]} N={N[g]}")
+    assert b.status() == (0, 0)
+    with pytest.raises(RuntimeError):  # not planned: refused before the library is called
+        W.Batch(seeds[:2], n[:2], N[:2]).tune_planned(out)
+
+
 def test_mixed_batch_graph_replays():
     # classes run on forked streams; captured in a graph, the fork and join
     # become parallel branches. Every replay continues each generator's

@@ -102,25 +102,42 @@ struct Lg<1> {
 constexpr int kThreads = 256;
 
 // A thread's T consecutive values of one component (16-, 8- or 4-byte
-// accesses).
-template <int T>
+// accesses). NT: nontemporal loads. The n = 4 fused pass reads its
+// permuted components with them (read once; the caches are left to the next
+// pass's permuted components, written in the same pass and read in the
+// next): at N = 2^22 that took the pass from 44.6 to 40.6 us on MI355X. The
+// permute kernel reads its source runs the same way.
+template <int T, bool NT>
 __device__ __forceinline__ void load_run(float (&x)[T], const float *p)
 {
     if constexpr (T % 4 == 0) {
 #pragma unroll
         for (int i = 0; i < T; i += 4) {
-            const v4f q = *reinterpret_cast<const v4f *>(p + i);
+            const v4f *src = reinterpret_cast<const v4f *>(p + i);
+            v4f q;
+            if constexpr (NT)
+                q = __builtin_nontemporal_load(src);
+            else
+                q = *src;
             x[i] = q.x;
             x[i + 1] = q.y;
             x[i + 2] = q.z;
             x[i + 3] = q.w;
         }
     } else if constexpr (T == 2) {
-        const v2f q = *reinterpret_cast<const v2f *>(p);
+        const v2f *src = reinterpret_cast<const v2f *>(p);
+        v2f q;
+        if constexpr (NT)
+            q = __builtin_nontemporal_load(src);
+        else
+            q = *src;
         x[0] = q.x;
         x[1] = q.y;
     } else {
-        x[0] = p[0];
+        if constexpr (NT)
+            x[0] = __builtin_nontemporal_load(p);
+        else
+            x[0] = p[0];
     }
 }
 
@@ -421,7 +438,8 @@ __global__ __launch_bounds__(kThreads) void k_stream_permute(Perm P)
 
     const float *src = P.X + (size_t)k * N + X0;
     for (uint32_t i = threadIdx.x * 4u; i < len; i += kThreads * 4u)
-        *reinterpret_cast<v4f *>(run + i) = *reinterpret_cast<const v4f *>(src + i);
+        *reinterpret_cast<v4f *>(run + i) =
+            __builtin_nontemporal_load(reinterpret_cast<const v4f *>(src + i));
     for (uint32_t w = threadIdx.x; w <= a; w += kThreads) {
         // ceil(num / a) through one correctly rounded FP64 division: |num| <
         // 2^32, and a non-integral quotient lies at least 1/a from an
@@ -538,6 +556,23 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
     if constexpr (NC == 2) rotation(sm64_next(rng), rcs, rsn);
     const int mat = (NC == 4) ? (int)P.mat : 0;
 
+    // the tuples' values first, so that the loads are in flight while the
+    // scale below is computed
+    const uint32_t j0 = (blockIdx.x * kThreads + threadIdx.x) * (uint32_t)T;
+    float X[NC][T];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        if constexpr (PERM) {
+            // plain loads: its new pool overwrites G in place, and
+            // nontemporal loads here cost 4-5 us per pass at n = 16, N = 2^20
+            load_run<T, false>(X[k], P.G + (size_t)k * N + j0);
+        } else {
+            const float *src = P.X + (size_t)k * N;
+#pragma unroll
+            for (int i = 0; i < T; ++i) X[k][i] = src[(a[k] * (j0 + i) + b[k]) & mask];
+        }
+    }
+
     // chi-squared scale from the old pool (section 4, eq. 3)
     const double xstar = (double)P.X[nu - 1];
     const double S = chi2_target(xstar, P.r_nu);
@@ -562,18 +597,6 @@ __global__ __launch_bounds__(kThreads) void k_stream_pass(Pass P)
     if (blockIdx.x == 0 && threadIdx.x == 0 && !__builtin_isfinite(c32))
         atomicOr(&P.state->flags, (uint32_t)WALLACE_FLAG_NONFINITE);
 
-    const uint32_t j0 = (blockIdx.x * kThreads + threadIdx.x) * (uint32_t)T;
-    float X[NC][T];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        if constexpr (PERM) {
-            load_run<T>(X[k], P.G + (size_t)k * N + j0);
-        } else {
-            const float *src = P.X + (size_t)k * N;
-#pragma unroll
-            for (int i = 0; i < T; ++i) X[k][i] = src[(a[k] * (j0 + i) + b[k]) & mask];
-        }
-    }
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         float v[NC];
@@ -713,6 +736,21 @@ __global__ __launch_bounds__(kFuseThreads) void k_stream_fuse(Fuse P)
     const uint32_t mask = N - 1u;
     const uint32_t nu = NC * N;
 
+    // Workgroups go round-robin to the 8 XCDs; block b takes tuple range
+    // cb = (b mod 8) G/8 + b/8 instead, so each XCD covers one contiguous
+    // eighth of the pool and the strand ends that adjacent ranges write to
+    // the same lines of G' meet in one L2 (n = 2: 3.5% per pass). The
+    // block's values are loaded first, so that the loads are in flight
+    // while the scale below is computed (0.7 us of 40.6 per pass at n = 4,
+    // N = 2^22). Nontemporal for n = 4 only: at n = 2, N = 2^23 they cost
+    // 1.3 us per pass (43.6 against 42.3).
+    const uint32_t cb = (gridDim.x % 8u) ? blockIdx.x
+                                          : (blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
+    const uint32_t j0 = cb * S + threadIdx.x * (uint32_t)T;
+    float X[NC][T];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) load_run<T, NC == 4>(X[k], P.G + (size_t)k * N + j0);
+
     double rcs = 0.0, rsn = 0.0;  // n = 2: the pass's rotation (draw n + 1)
     if constexpr (NC == 2) {
         uint64_t rng = P.rng + (uint64_t)NC * 0x9E3779B97F4A7C15ull;
@@ -743,16 +781,6 @@ __global__ __launch_bounds__(kFuseThreads) void k_stream_fuse(Fuse P)
     if (blockIdx.x == 0 && threadIdx.x == 0 && !__builtin_isfinite(c32))
         atomicOr(&P.state->flags, (uint32_t)WALLACE_FLAG_NONFINITE);
 
-    // Workgroups go round-robin to the 8 XCDs; block b takes tuple range
-    // cb = (b mod 8) G/8 + b/8 instead, so each XCD covers one contiguous
-    // eighth of the pool and the strand ends that adjacent ranges write to
-    // the same lines of G' meet in one L2 (n = 2: 3.5% per pass)
-    const uint32_t cb = (gridDim.x % 8u) ? blockIdx.x
-                                          : (blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
-    const uint32_t j0 = cb * S + threadIdx.x * (uint32_t)T;
-    float X[NC][T];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) load_run<T>(X[k], P.G + (size_t)k * N + j0);
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         float v[NC];

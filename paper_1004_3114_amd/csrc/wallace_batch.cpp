@@ -149,6 +149,13 @@ hipError_t upload_jobs(wallace_batch *b, const std::vector<Job> &jobs, hipStream
     return hipStreamSynchronize(s);
 }
 
+// Where a launch's generators keep their states and pools: the workspace,
+// or (the autotuner's runs) a copy of that region laid out the same way.
+struct StateBase {
+    GenState *states = nullptr;
+    float *pools = nullptr;
+};
+
 // One launch per class. Several classes are spread over up to kClassLanes
 // streams (the caller's and side streams forked from it and joined back).
 // Latency-bound classes run first, one after another, on the caller's
@@ -157,8 +164,17 @@ hipError_t upload_jobs(wallace_batch *b, const std::vector<Job> &jobs, hipStream
 // chains of the small pools overlap the bandwidth-bound classes instead of
 // trailing them. Under graph capture the fork and join become parallel
 // branches of the graph.
-hipError_t launch_classes(wallace_batch *b, float *out, uint32_t sigma_mode, hipStream_t s)
+hipError_t launch_classes(wallace_batch *b, float *out, uint32_t sigma_mode, hipStream_t s,
+                          const StateBase *alt = nullptr)
 {
+    auto args = [&](const ClassInfo &c) {
+        PoolArgs a = class_args(b, c, out, sigma_mode);
+        if (alt) {
+            a.states = alt->states;
+            a.pools = alt->pools;
+        }
+        return a;
+    };
     std::vector<const ClassInfo *> live;
     for (const ClassInfo &c : b->classes)
         if (c.job_count) live.push_back(&c);
@@ -166,7 +182,7 @@ hipError_t launch_classes(wallace_batch *b, float *out, uint32_t sigma_mode, hip
     if (!b->own_side) nside = std::min<int>(nside, (int)b->side.size());
     if (nside <= 0) {
         for (const ClassInfo *c : live) {
-            hipError_t e = launch_pool(c->sched, class_args(b, *c, out, sigma_mode), c->grid, s);
+            hipError_t e = launch_pool(c->sched, args(*c), c->grid, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -195,7 +211,7 @@ hipError_t launch_classes(wallace_batch *b, float *out, uint32_t sigma_mode, hip
     if (split) {
         for (const ClassInfo *c : small) {
             if (e != hipSuccess) break;
-            e = launch_pool(c->sched, class_args(b, *c, out, sigma_mode), c->grid, s);
+            e = launch_pool(c->sched, args(*c), c->grid, s);
         }
         live = big;
     }
@@ -205,7 +221,7 @@ hipError_t launch_classes(wallace_batch *b, float *out, uint32_t sigma_mode, hip
         if (e != hipSuccess) break;
         const int lane = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[lane] += c->work;
-        e = launch_pool(c->sched, class_args(b, *c, out, sigma_mode), c->grid,
+        e = launch_pool(c->sched, args(*c), c->grid,
                         lane == 0 ? s : b->side[lane - 1]);
     }
     for (int i = 0; i < nside && e == hipSuccess; ++i) {
@@ -497,11 +513,35 @@ int32_t wallace_batch_tune_planned(wallace_batch *b, float *d_out, uint64_t out_
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *copy = static_cast<char *>(d_scratch);
     const uint32_t rm = (uint32_t)b->opts.reduce_mode;
+    const uint32_t sm = b->opts.check_workspace ? 1u : 0u;
+    const StateBase alt{reinterpret_cast<GenState *>(copy),
+                        reinterpret_cast<float *>(copy + (b->lay.pools - b->lay.states))};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipError_t e = hipEventCreate(&ev0);
     if (e == hipSuccess) e = hipEventCreate(&ev1);
-    for (ClassInfo &c : b->classes) {
-        if (e != hipSuccess || c.job_count == 0) continue;
+    // ms of `run` on a fresh copy of the states and pools: the fastest of
+    // two timed runs after an untimed one
+    auto timed = [&](auto run, float *ms) {
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = hipMemcpyAsync(copy, b->ws + b->lay.states, region, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipEventRecord(ev0, s);
+            if (e == hipSuccess) e = run();
+            if (e == hipSuccess) e = hipEventRecord(ev1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(ev1);
+            float ts = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ts, ev0, ev1);
+            if (rep > 0) *ms = (rep == 1) ? ts : std::min(*ms, ts);
+        }
+    };
+    // Each class alone: every candidate schedule, the fastest kept.
+    std::vector<std::vector<std::pair<Sched, float>>> alone(b->classes.size());
+    double total_work = 0.0;
+    int live = 0;
+    for (size_t ci = 0; ci < b->classes.size() && e == hipSuccess; ++ci) {
+        ClassInfo &c = b->classes[ci];
+        if (c.job_count == 0) continue;
+        total_work += c.work;
+        ++live;
         Sched cand[32];
         const int nc = candidate_scheds(c.n, c.N, cand, 32);
         float best_ms = 1e30f;
@@ -511,22 +551,14 @@ int32_t wallace_batch_tune_planned(wallace_batch *b, float *d_out, uint64_t out_
             t.sched = cand[i];
             e = class_grid(t, b->cus, rm);
             if (e != hipSuccess) break;
-            PoolArgs a = class_args(b, t, d_out, 0);
-            a.states = reinterpret_cast<GenState *>(copy);
-            a.pools = reinterpret_cast<float *>(copy + (b->lay.pools - b->lay.states));
+            PoolArgs a = class_args(b, t, d_out, sm);
+            a.states = alt.states;
+            a.pools = alt.pools;
             float ms = 0.0f;
-            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-                e = hipMemcpyAsync(copy, b->ws + b->lay.states, region,
-                                   hipMemcpyDeviceToDevice, s);
-                if (e == hipSuccess) e = hipEventRecord(ev0, s);
-                if (e == hipSuccess) e = launch_pool(t.sched, a, t.grid, s);
-                if (e == hipSuccess) e = hipEventRecord(ev1, s);
-                if (e == hipSuccess) e = hipEventSynchronize(ev1);
-                float ts = 0.0f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ts, ev0, ev1);
-                if (rep > 0) ms = (rep == 1) ? ts : std::min(ms, ts);
-            }
-            if (e == hipSuccess && ms < best_ms) {
+            timed([&]() { return launch_pool(t.sched, a, t.grid, s); }, &ms);
+            if (e != hipSuccess) break;
+            alone[ci].push_back({cand[i], ms});
+            if (ms < best_ms) {
                 best_ms = ms;
                 best_i = i;
             }
@@ -535,6 +567,53 @@ int32_t wallace_batch_tune_planned(wallace_batch *b, float *d_out, uint64_t out_
         c.sched = cand[best_i];
         e = class_grid(c, b->cus, rm);
         record_tuned(c.n, c.N, c.sched, best_ms * 1000.0);
+    }
+    // Then the whole fill. Its classes run side by side and share the GPU,
+    // so a class's fastest schedule alone need not be its best in the fill.
+    // Each class with at least 1/20 of the values tries the schedules that
+    // came within 25% of its best alone; one replaces the current choice
+    // only if the whole fill gets at least 0.5% faster.
+    if (e == hipSuccess && live > 1) {
+        auto fill = [&]() { return launch_classes(b, d_out, sm, s, &alt); };
+        float cur_ms = 0.0f;
+        timed(fill, &cur_ms);
+        std::vector<size_t> order;
+        for (size_t ci = 0; ci < b->classes.size(); ++ci)
+            if (b->classes[ci].job_count && b->classes[ci].work >= total_work / 20.0)
+                order.push_back(ci);
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            return b->classes[x].work > b->classes[y].work;
+        });
+        for (size_t ci : order) {
+            if (e != hipSuccess) break;
+            ClassInfo &c = b->classes[ci];
+            float best_alone = 1e30f;
+            for (const auto &pr : alone[ci]) best_alone = std::min(best_alone, pr.second);
+            const Sched kept = c.sched;
+            for (const auto &pr : alone[ci]) {
+                if (e != hipSuccess) break;
+                const Sched &cs = pr.first;
+                if ((cs.T == c.sched.T && cs.L == c.sched.L && cs.C == c.sched.C) ||
+                    pr.second > 1.25f * best_alone)
+                    continue;
+                const Sched prev = c.sched;
+                c.sched = cs;
+                e = class_grid(c, b->cus, rm);
+                float ms = 0.0f;
+                if (e == hipSuccess) timed(fill, &ms);
+                if (e == hipSuccess && ms < 0.995f * cur_ms) {
+                    cur_ms = ms;
+                } else if (e == hipSuccess) {
+                    c.sched = prev;
+                    e = class_grid(c, b->cus, rm);
+                }
+            }
+            if (e == hipSuccess && !(c.sched.T == kept.T && c.sched.L == kept.L && c.sched.C == kept.C)) {
+                for (const auto &pr : alone[ci])
+                    if (pr.first.T == c.sched.T && pr.first.L == c.sched.L && pr.first.C == c.sched.C)
+                        record_tuned(c.n, c.N, c.sched, pr.second * 1000.0);
+            }
+        }
     }
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);

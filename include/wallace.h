@@ -240,14 +240,15 @@ int32_t wallace_batch_set_streams(wallace_batch *b, uint32_t count, void *const 
  * the fastest and records it in the tuning cache file named by the
  * environment variable WALLACE_TUNE_CACHE (if set). The generators' state is
  * not touched. All candidates give bit-identical output. Synchronises.
- * The environment variable WALLACE_SCHED="n:N:T:L:C,..." (read at every
- * wallace_batch_init and wallace_init) forces the schedule of a class or of
- * a single on-chip generator: L lanes per pool, T tuples per lane (T*L = N),
- * C components per on-chip stage. The first entry naming a class must be a
- * compiled shape, else wallace_batch_init or wallace_init returns
- * WALLACE_EINVAL. Without it a single generator spreads its pool over up to
- * 1024 lanes (its pass is a latency chain), while a batch uses one wave or
- * less per pool. */
+ * The environment variable WALLACE_SCHED="n:N:T:L:C,..." (read by every
+ * wallace_batch_init and wallace_init, and by both autotuners) forces the
+ * schedule of a class or of a single on-chip generator: L lanes per pool, T
+ * tuples per lane (T*L = N), C components per on-chip stage. The first entry
+ * naming a class must be a compiled shape, else wallace_batch_init or
+ * wallace_init returns WALLACE_EINVAL; the autotuners keep a class forced
+ * this way as it is. Without it a single generator spreads its pool over up
+ * to 1024 lanes (its pass is a latency chain), while a batch uses one wave
+ * or less per pool. */
 int32_t wallace_batch_tune_bytes(wallace_batch *b, size_t *bytes);
 int32_t wallace_batch_tune(wallace_batch *b, void *d_scratch,
                            size_t scratch_bytes, void *stream);

@@ -542,6 +542,8 @@ int32_t wallace_batch_tune_planned(wallace_batch *b, float *d_out, uint64_t out_
         if (c.job_count == 0) continue;
         total_work += c.work;
         ++live;
+        Sched forced;
+        if (forced_sched(c.n, c.N, &forced) > 0) continue;  // WALLACE_SCHED: kept as forced
         Sched cand[32];
         const int nc = candidate_scheds(c.n, c.N, cand, 32);
         float best_ms = 1e30f;
@@ -627,6 +629,8 @@ int32_t wallace_batch_tune(wallace_batch *b, void *d_scratch, size_t scratch_byt
     if (!b || !d_scratch || (((uintptr_t)d_scratch) & (kAlign - 1))) return WALLACE_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (ClassInfo &c : b->classes) {
+        Sched forced;
+        if (forced_sched(c.n, c.N, &forced) > 0) continue;  // WALLACE_SCHED: kept as forced
         if (scratch_bytes < tune_scratch_bytes(c.n, c.N)) return WALLACE_ENOSPC;
         const GenState *st = reinterpret_cast<const GenState *>(b->ws + b->lay.states) + c.gens[0];
         const float *pool = reinterpret_cast<const float *>(b->ws + b->lay.pools) +

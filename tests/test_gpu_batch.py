@@ -262,6 +262,40 @@ def test_forced_schedule_that_is_not_compiled_is_rejected(monkeypatch):
     W.Generator(1, 4, 256)
 
 
+def test_autotuners_keep_a_forced_schedule(tmp_path, monkeypatch):
+    # A class forced through WALLACE_SCHED keeps its schedule through both
+    # autotuners; the other classes are tuned as usual, and the fill stays
+    # exact. Here the forced shape (2 tuples on 128 lanes) is not the
+    # default one (4 on 64).
+    _dev()
+    monkeypatch.setenv("WALLACE_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    monkeypatch.setenv("WALLACE_SCHED", "4:256:2:128:4")
+    G = 12
+    seeds = np.arange(1500, 1500 + G, dtype=np.uint64)
+    n = np.array([4] * 6 + [16] * 6, dtype=np.int32)
+    N = np.array([256] * 6 + [1024] * 6, dtype=np.uint32)
+    passes = np.full(G, 3, dtype=np.uint32)
+    nu = n.astype(np.uint64) * N
+    off = np.zeros(G, np.uint64)
+    np.cumsum((nu * 3)[:-1], out=off[1:])
+    total = int((nu * 3).sum())
+    print(f"case forced schedule through the autotuners G={G}", flush=True)
+    b = W.Batch(seeds, n, N)
+    b.tune()
+    b.plan(off, passes)
+    out = torch.empty(total, dtype=torch.float32, device="cuda")
+    b.tune_planned(out)
+    cls = {(c["n"], c["N"]): c for c in b.classes()}
+    assert (cls[(4, 256)]["T"], cls[(4, 256)]["L"], cls[(4, 256)]["C"]) == (2, 128, 4)
+    out.fill_(float("nan"))
+    b.fill(out)
+    host = out.cpu().numpy()
+    for g in (0, 5, 6, 11):
+        ref = oracle_generator_output(seeds[g], n[g], N[g], 3)
+        assert_bits_equal(host[int(off[g]):int(off[g]) + int(nu[g]) * 3], ref, f"gen {g}")
+    assert b.status() == (0, 0)
+
+
 def test_tuner_runs_and_keeps_state(tmp_path, monkeypatch):
     _dev()
     monkeypatch.setenv("WALLACE_TUNE_CACHE", str(tmp_path / "tune.txt"))

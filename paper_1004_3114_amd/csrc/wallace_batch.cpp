@@ -100,6 +100,11 @@ struct wallace_batch {
 
 namespace {
 
+bool same_sched(const Sched &x, const Sched &y)
+{
+    return x.T == y.T && x.L == y.L && x.C == y.C;
+}
+
 hipError_t class_grid(ClassInfo &c, int cus, uint32_t rmode)
 {
     int per_cu = 0;
@@ -595,9 +600,7 @@ int32_t wallace_batch_tune_planned(wallace_batch *b, float *d_out, uint64_t out_
             for (const auto &pr : alone[ci]) {
                 if (e != hipSuccess) break;
                 const Sched &cs = pr.first;
-                if ((cs.T == c.sched.T && cs.L == c.sched.L && cs.C == c.sched.C) ||
-                    pr.second > 1.25f * best_alone)
-                    continue;
+                if (same_sched(cs, c.sched) || pr.second > 1.25f * best_alone) continue;
                 const Sched prev = c.sched;
                 c.sched = cs;
                 e = class_grid(c, b->cus, rm);
@@ -610,10 +613,9 @@ int32_t wallace_batch_tune_planned(wallace_batch *b, float *d_out, uint64_t out_
                     e = class_grid(c, b->cus, rm);
                 }
             }
-            if (e == hipSuccess && !(c.sched.T == kept.T && c.sched.L == kept.L && c.sched.C == kept.C)) {
+            if (e == hipSuccess && !same_sched(c.sched, kept)) {
                 for (const auto &pr : alone[ci])
-                    if (pr.first.T == c.sched.T && pr.first.L == c.sched.L && pr.first.C == c.sched.C)
-                        record_tuned(c.n, c.N, c.sched, pr.second * 1000.0);
+                    if (same_sched(pr.first, c.sched)) record_tuned(c.n, c.N, c.sched, pr.second * 1000.0);
             }
         }
     }

@@ -168,6 +168,16 @@ def _sylvester(n):
     return H
 
 
+def test_sylvester_hadamard_matches_library():
+    # the Hadamard matrices behind A0 and H16 (section 3), against scipy's
+    # Sylvester construction
+    import scipy.linalg
+    for n in (2, 4, 16):
+        assert np.array_equal(_sylvester(n), scipy.linalg.hadamard(n))
+    assert np.array_equal(oracle.matrix(16, 0) * 4.0, scipy.linalg.hadamard(16))
+    assert np.array_equal(oracle.matrix(4, 0) * 2.0, scipy.linalg.hadamard(4))
+
+
 def _expected_matrix(n, mat):
     if n == 4 and mat == 1:
         return 0.5 * np.ones((4, 4)) - np.eye(4)
